@@ -1,0 +1,5 @@
+"""Host FP64 construction of the butterfly factor set (the input of the GPU apply)."""
+from .trees import box_bisection_tree, frequency_tree, depth_for, node_range
+from .interp import column_id
+from .build import build_factors
+from .fourier import real_modes, FourierBlocks

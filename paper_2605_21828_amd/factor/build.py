@@ -1,0 +1,131 @@
+"""Level-by-level butterfly factorization with column IDs (host, FP64).
+
+Follows the butterfly factorization (Sec. 2, Alg. "Butterfly factorization"):
+level 0 factors each frequency-leaf column block, levels 1..L re-factor the
+concatenated previous-level bases restricted to the current space node, and the
+leaf column bases are kept at the end.  With column IDs the previous level's
+column basis restricted to tau is Phi(tau, J) for the previous skeleton J, so a
+block at level l is simply Phi(tau_i, [J_{l-1,p,2j}, J_{l-1,p,2j+1}]) and only
+entries of Phi are needed (the property that makes the streaming variant of
+Sec. 4 possible).  Blocks of one level are independent and run in a process
+pool; skeletons of the previous level are the only state passed on.
+
+`blocks(rows, cols)` must return Phi[rows][:, cols] in float64; rows=None means
+all points.
+"""
+import os
+import time
+
+import numpy as np
+
+from .interp import column_id
+
+_CTX = {}
+
+
+def _id_task(task):
+    lvl, q, a, b, cols = task
+    blocks, perm, tol = _CTX["blocks"], _CTX["perm"], _CTX["tol"]
+    rows = None if lvl == 0 else perm[a:b]
+    if cols.size == 0:
+        return lvl, q, cols, None, True
+    A = blocks(rows, cols)
+    J, P, ident = column_id(A, tol)
+    return lvl, q, cols[J], P, ident
+
+
+def _init_worker():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _run(tasks, workers):
+    if workers <= 1:
+        return [_id_task(t) for t in tasks]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers, initializer=_init_worker) as pool:
+        return list(pool.imap_unordered(_id_task, tasks, chunksize=max(1, len(tasks) // (8 * workers))))
+
+
+def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=None):
+    """Build the factor set dict (schema documented in `io.py`)."""
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    nb = 1 << L
+    perm_x = np.asarray(perm_x, dtype=np.int32)
+    xoff = np.asarray(xoff, dtype=np.int64)
+    koff = np.asarray(koff, dtype=np.int64)
+    _CTX.update(blocks=blocks, perm=perm_x, tol=float(tol))
+    rank = np.zeros((L + 1, nb), dtype=np.int32)
+    ident = np.zeros((L + 1, nb), dtype=np.uint8)
+    P_blocks = [[None] * nb for _ in range(L + 1)]
+    J_prev = None
+    stats = []
+    for lvl in range(L + 1):
+        t0 = time.time()
+        tasks = []
+        if lvl == 0:
+            for j in range(nb):
+                tasks.append((0, j, 0, n, np.arange(koff[j], koff[j + 1], dtype=np.int64)))
+        else:
+            nf = 1 << (L - lvl)
+            w = 1 << (L - lvl)   # leaves per space node at depth lvl
+            for i in range(1 << lvl):
+                a, b = int(xoff[i * w]), int(xoff[(i + 1) * w])
+                p = i >> 1
+                for j in range(nf):
+                    q1 = p * (2 * nf) + 2 * j
+                    cols = np.concatenate([J_prev[q1], J_prev[q1 + 1]])
+                    tasks.append((lvl, i * nf + j, a, b, cols))
+        J_cur = [None] * nb
+        for _, q, J, P, idf in _run(tasks, workers):
+            J_cur[q] = J
+            rank[lvl, q] = len(J)
+            ident[lvl, q] = 1 if idf else 0
+            P_blocks[lvl][q] = P
+        J_prev = J_cur
+        st = dict(level=lvl, seconds=round(time.time() - t0, 3),
+                  rank_min=int(rank[lvl].min()), rank_max=int(rank[lvl].max()),
+                  rank_mean=float(rank[lvl].mean()), ident=int(ident[lvl].sum()))
+        stats.append(st)
+        if log:
+            log(st)
+    # leaf column bases U_i = Phi(tau_i, J_{L,i})
+    U_list = []
+    for i in range(nb):
+        rows = perm_x[xoff[i]:xoff[i + 1]]
+        cols = J_prev[i]
+        if rows.size and cols.size:
+            U_list.append(np.ascontiguousarray(blocks(rows, cols)))
+        else:
+            U_list.append(np.zeros((rows.size, cols.size)))
+    P_off = np.full((L + 1, nb), -1, dtype=np.int64)
+    chunks, off = [], 0
+    for lvl in range(L + 1):
+        for q in range(nb):
+            P = P_blocks[lvl][q]
+            if P is not None and not ident[lvl, q]:
+                P_off[lvl, q] = off
+                chunks.append(np.ascontiguousarray(P, dtype=np.float64).ravel())
+                off += P.size
+    U_off = np.zeros(nb, dtype=np.int64)
+    uchunks, uo = [], 0
+    for i in range(nb):
+        U_off[i] = uo
+        uchunks.append(U_list[i].ravel())
+        uo += U_list[i].size
+    return dict(
+        n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol),
+        perm_x=perm_x, xoff=xoff, koff=koff, rank=rank, ident=ident,
+        P=np.concatenate(chunks) if chunks else np.zeros(0),
+        P_off=P_off,
+        U=np.concatenate(uchunks) if uchunks else np.zeros(0),
+        U_off=U_off,
+        skel_L=np.concatenate([J_prev[i] for i in range(nb)]).astype(np.int64),
+        build_stats=np.array([[s["level"], s["seconds"], s["rank_min"], s["rank_max"],
+                               s["rank_mean"], s["ident"]] for s in stats]),
+    )
