@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the butterfly manifold harmonic transform apply on one MI355X.
+
+One step = one FP32 synthesis f = Phi~ c plus one FP32 analysis g = Phi~^T f
+on a block of nrhs right-hand sides, inputs resident in HBM.  The metric is
+RHS*points per second over both directions: 2 * n * nrhs / seconds_per_step.
+The same inputs are also run through the plain FP64 GPU apply for the speedup
+figure.  The workload is the nonuniform periodic square: 65536 i.i.d. points,
+16384 real Fourier modes, leaf 128 (L = 9), ID tolerance 1e-8, 64 RHS with
+coefficients N(0,1) / (1 + |k|^2).  Factors are built on the host in FP64
+before timing (not timed).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"f64": ("mfma", 78.6, "TFLOP/s"), "f32": ("mfma", 157.3, "TFLOP/s")}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def event_time(fn, reps, torch):
+    """Average milliseconds of fn() over reps, measured with HIP events on the current stream."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def cpu_baseline(fs, pts, c_host, f_host, out32, g32, rows, cols, lam):
+    """The oracle as it stands, timed on the host cores, plus the accuracy check.
+
+    Times the oracle's butterfly apply and its transpose (O2, NumPy) on a
+    bounded sample of 4 right-hand sides of the same factors; reports
+    RHS*points/s over both directions.  Then measures the GPU FP32 results
+    against the dense FP64 transform (O1) on sampled rows and columns.
+    """
+    from oracle import butterfly as ob
+    from oracle import dense as od
+    from oracle import modes as om
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    b_s = 4
+    t0 = time.time()
+    ob.apply(fs, c_host[:, :b_s])
+    ob.apply_transpose(fs, f_host[:, :b_s])
+    dt = time.time() - t0
+    n = int(fs["n"])
+    md = om.fourier_modes(int(fs["m"]))
+    err_f = od.rel_err_cols(out32[rows], od.fourier_synthesis_rows(pts, md, rows, c_host))[0]
+    err_g = od.rel_err_cols(g32[cols], od.fourier_analysis_cols(pts, md, cols, f_host))[0]
+    base = {"value": 2.0 * n * b_s / dt, "unit": "RHS*points/s", "cores": int(cores), "kind": "oracle",
+            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors on %d of the RHS, %.1f s"
+                      % (b_s, dt)}
+    return base, {"synthesis_rows_sampled": len(rows), "synthesis_rel_err": err_f,
+                  "analysis_cols_sampled": len(cols), "analysis_rel_err": err_g}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="iid65536")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+    from paper_2605_21828_amd.factor.fourier import real_modes
+
+    w = wl.WORKLOADS[args.workload]
+    n, m, b = w["n"], w["m"], w["nrhs"]
+    pts = wl.points_for(w)
+    log("building factors: n=%d m=%d leaf=%d tol=%g" % (n, m, w["leaf"], w["tol"]))
+    fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=False,
+                                log=lambda s: log("  factor", s))
+    F = fio.stored_entries(fs)
+    modes = real_modes(m)
+    lam = (modes[:, 0] ** 2 + modes[:, 1] ** 2).astype(np.float64)
+    c_host = wl.coefficients(w["wid"], m, b, lam=lam, kind=w["coef"])
+    f_host = wl.values(w["wid"], n, b)
+
+    dev = torch.device("cuda:0")
+    log("uploading FP32 plan")
+    p32 = Plan(fs, "f32", max_nrhs=b, device=dev)
+    c32 = torch.tensor(c_host, dtype=torch.float32, device=dev)
+    f32 = torch.tensor(f_host, dtype=torch.float32, device=dev)
+    y32 = torch.empty((n, b), dtype=torch.float32, device=dev)
+    g32 = torch.empty((m, b), dtype=torch.float32, device=dev)
+
+    def step():
+        p32.apply(c32, out=y32)
+        p32.apply_t(f32, out=g32)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log("fp32 step %.3f ms" % ms)
+
+    # per-direction timings with HIP events (torch's current stream is the one the library launches on)
+    reps = max(args.steps, 5)
+    ms_fwd = event_time(lambda: p32.apply(c32, out=y32), reps, torch)
+    ms_bwd = event_time(lambda: p32.apply_t(f32, out=g32), reps, torch)
+    launches = int(fs["L"]) + 2   # stage-0, L transfer levels, final stage
+    flops = 2.0 * F * b
+    alg_bytes32 = 4.0 * F + 4.0 * (n + m) * b
+    achieved = flops / (ms_fwd * 1e-3) / 1e12
+    result_extra = {
+        "fp32_apply_ms": ms_fwd, "fp32_apply_transpose_ms": ms_bwd,
+        "fp32_apply_alg_GBps": alg_bytes32 / (ms_fwd * 1e-3) / 1e9,
+        "stored_factor_entries": F, "compression_vs_dense": n * m / F,
+        "stage_launches_per_apply": launches,
+    }
+
+    if not args.no_f64:
+        log("uploading FP64 plan")
+        del_fp = None
+        p64 = Plan(fs, "f64", max_nrhs=b, device=dev)
+        c64 = torch.tensor(c_host, dtype=torch.float64, device=dev)
+        f64 = torch.tensor(f_host, dtype=torch.float64, device=dev)
+        y64 = torch.empty((n, b), dtype=torch.float64, device=dev)
+        g64 = torch.empty((m, b), dtype=torch.float64, device=dev)
+        for _ in range(2):
+            p64.apply(c64, out=y64)
+            p64.apply_t(f64, out=g64)
+        ms64_fwd = event_time(lambda: p64.apply(c64, out=y64), reps, torch)
+        ms64_bwd = event_time(lambda: p64.apply_t(f64, out=g64), reps, torch)
+        d32 = y32.double()
+        rel = float(torch.linalg.norm(d32 - y64) / torch.linalg.norm(y64))
+        result_extra.update({
+            "fp64_plain_apply_ms": ms64_fwd, "fp64_plain_apply_transpose_ms": ms64_bwd,
+            "speedup_fp32_vs_fp64_plain": (ms64_fwd + ms64_bwd) / (ms_fwd + ms_bwd),
+            "fp32_vs_fp64_gpu_rel_err": rel,
+        })
+        del p64, c64, f64, y64, g64, d32, del_fp
+        torch.cuda.empty_cache()
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        rows = wl.sample_indices(w["wid"], n, 2048)
+        cols = wl.sample_indices(w["wid"], m, 2048, stream=4)
+        out_np = y32.double().cpu().numpy()
+        g_np = g32.double().cpu().numpy()
+        base, acc = cpu_baseline(fs, pts, c_host, f_host, out_np, g_np, rows, cols, lam)
+        result_extra.update(acc)
+
+    bound, peak, unit = PEAK["f32"]
+    res = {
+        "metric": "butterfly apply RHS*points/s (FP32 synthesis + analysis)",
+        "value": 2.0 * n * b / (ms * 1e-3),
+        "unit": "RHS*points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
+                   "L": int(fs["L"]), "step": "apply + apply_transpose"},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "fwd_stage_kernel<float,64> (all stage launches of one FP32 apply)",
+                     "per_launch_alg_flops": flops / launches,
+                     "avg_launch_ms": ms_fwd / launches},
+        "cpu_baseline": base,
+        "extra": result_extra,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * bfmht.h -- C ABI of the MI355X (gfx950) butterfly manifold harmonic transform.
+ *
+ * The transform is the matrix form of the manifold harmonic transform,
+ * f = Phi c with Phi[j, k] = phi_k(x_j) (Sec. 1, eq. MHT-sum), and its adjoint,
+ * which maps point values back to coefficients; Phi is real, so the adjoint is
+ * Phi^T (Sec. 1, the adjoint transform).  Phi is given as a row-wise butterfly
+ * factor set built on the host (Sec. 2, Alg. "Butterfly factorization" and the
+ * set it returns: a basis per frequency leaf, a transfer block per block pair at
+ * levels 1..L, a column basis per space leaf).  Construction stays on the host
+ * in FP64; this library only uploads and applies the factors.
+ *
+ * Conventions
+ *  - Both trees are complete binary trees of depth L.  At level l (0..L) space
+ *    node i sits at depth l and frequency node j at depth L-l; the block id is
+ *    q = i * 2^(L-l) + j ("space-major").  The two inputs of block (l, i, j) are
+ *    blocks (l-1, i>>1, 2j) and (l-1, i>>1, 2j+1).
+ *  - Column bases are submatrices of Phi (column interpolative decompositions),
+ *    so a block (l, i, j) computes y_lij = P_lij [y_{l-1,i>>1,2j}; y_{l-1,i>>1,2j+1}],
+ *    level 0 computes y_0j = P_0j c[koff[j] : koff[j+1]], and the last stage
+ *    writes f[perm_x[xoff[i] + t]] = (U_i y_Li)[t].
+ *  - Dense right-hand-side blocks are row-major: row r, column (RHS) s at
+ *    ptr[r * ld + s], ld >= nrhs.  Rows are points (f) or modes (c).
+ *  - All device pointers are caller-owned (PyTorch allocates them).  The plan
+ *    owns host metadata only and refers to device memory inside the buffer
+ *    given to bfmht_plan_upload.
+ *  - Every call that takes a stream is asynchronous on that stream (a
+ *    hipStream_t passed as void*; NULL = the default stream) and never
+ *    synchronises, except bfmht_plan_upload, which synchronises its stream
+ *    once before freeing its host staging copy.
+ *  - Errors: every call returns a status; bfmht_last_error() gives a message
+ *    for the calling thread.  No exception crosses the ABI.  nrhs == 0 is a
+ *    no-op that returns BFMHT_OK.
+ */
+#ifndef BFMHT_H
+#define BFMHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfmht_plan bfmht_plan;
+
+/* Arithmetic of the apply.  F64: factors, level vectors and I/O in double
+ * (the plain baseline).  F32: factors and vectors in float, FP32 MFMA with
+ * FP32 accumulation.  BF16X2 / BF16X3: factors pre-split at upload into 2 / 3
+ * bfloat16 terms (hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo),
+ * round to nearest even), activations split the same way per tile, BF16 MFMA
+ * products hi*hi + hi*lo + lo*hi (X2) or the six products whose term indices
+ * sum to at most 2 (X3), FP32 accumulation, FP32 level vectors and I/O. */
+typedef enum {
+  BFMHT_F64 = 0,
+  BFMHT_F32 = 1,
+  BFMHT_BF16X2 = 2,
+  BFMHT_BF16X3 = 3
+} bfmht_precision;
+
+typedef enum {
+  BFMHT_OK = 0,
+  BFMHT_EINVAL = 1,   /* bad argument: null pointer, size, ld, inconsistent factors */
+  BFMHT_ESTATE = 2,   /* call out of order, e.g. apply before upload */
+  BFMHT_ENOSPACE = 3, /* device buffer or workspace smaller than required */
+  BFMHT_EHIP = 4      /* a HIP runtime call failed */
+} bfmht_status;
+
+/* Host FP64 factor set (Sec. 2, the factor set returned by the factorization).
+ * Caller-owned; read only during bfmht_plan_create, which copies what it needs.
+ *  n, m      number of points (rows of Phi) and modes (columns), m, n >= 0
+ *  L         tree depth, 0 <= L <= 24
+ *  perm_x    [n]      tree position -> original point index (a permutation)
+ *  xoff      [2^L+1]  space-leaf offsets into tree positions, xoff[0] = 0, xoff[2^L] = n
+ *  koff      [2^L+1]  frequency-leaf offsets into columns (eigenvalue order), koff[2^L] = m
+ *  rank      [(L+1) * 2^L]  r_{l,q} at rank[l * 2^L + q]
+ *  ident     [(L+1) * 2^L]  1 where P_{l,q} is the identity (then r_{l,q} equals its
+ *                           input row count and nothing is stored)
+ *  P, P_off  P_{l,q} is rank x r_in, row-major, at P + P_off[l * 2^L + q]
+ *            (r_in = koff[j+1]-koff[j] at level 0, else the two input ranks summed);
+ *            P_off is ignored for identity blocks
+ *  P_len     number of doubles readable at P (bounds check of P_off)
+ *  U, U_off  U_i is (xoff[i+1]-xoff[i]) x rank[L * 2^L + i], row-major, at U + U_off[i]
+ *  U_len     number of doubles readable at U */
+typedef struct {
+  int64_t n, m;
+  int32_t L;
+  const int32_t *perm_x;
+  const int64_t *xoff;
+  const int64_t *koff;
+  const int32_t *rank;
+  const uint8_t *ident;
+  const double *P;
+  const int64_t *P_off;
+  int64_t P_len;
+  const double *U;
+  const int64_t *U_off;
+  int64_t U_len;
+} bfmht_factors_host;
+
+/* Validate the factor set and build the device layout for one precision.
+ * On success *plan owns host metadata (stage tables, converted factors staged
+ * for upload); on failure *plan is set to NULL.  max_nrhs >= 1 bounds the nrhs
+ * of later applies (it sizes nothing on the device; workspace is per call). */
+bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precision prec,
+                               int32_t max_nrhs, bfmht_plan **plan);
+
+/* Bytes of device memory the plan needs for its factors and tables. */
+int64_t bfmht_plan_device_bytes(const bfmht_plan *plan);
+
+/* Bytes of workspace one apply or apply_transpose with this nrhs needs
+ * (two ping-pong level buffers); -1 on a bad argument. */
+int64_t bfmht_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
+
+/* Copy the plan's factors and tables into dev_buf (device memory, at least
+ * bfmht_plan_device_bytes bytes, 256-byte aligned), on `stream`; synchronises
+ * that stream, then frees the host staging copy.  The plan keeps dev_buf's
+ * address; the caller keeps dev_buf alive until bfmht_plan_destroy.  A plan is
+ * uploaded once; ESTATE on a second upload. */
+bfmht_status bfmht_plan_upload(bfmht_plan *plan, void *dev_buf, int64_t dev_bytes, void *stream);
+
+/* Synthesis f = Phi~ c.  c: device, m x nrhs (ld ldc); f: device, n x nrhs
+ * (ld ldf), fully overwritten.  Element type double for F64, float otherwise.
+ * ws: device workspace of at least bfmht_workspace_bytes(plan, nrhs) bytes,
+ * 256-byte aligned.  c and f must not overlap ws or each other. */
+bfmht_status bfmht_apply(const bfmht_plan *plan, const void *c, int64_t ldc, void *f, int64_t ldf,
+                         int32_t nrhs, void *ws, int64_t ws_bytes, void *stream);
+
+/* Analysis g = Phi~^T f: the exact transpose of bfmht_apply's steps, in
+ * reverse order.  f: device n x nrhs (ld ldf); g: device m x nrhs (ld ldg),
+ * fully overwritten.  Same workspace rule as bfmht_apply. */
+bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_t ldf, void *g,
+                                   int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
+                                   void *stream);
+
+/* Free the plan's host memory.  Does not touch device memory.  NULL is a no-op. */
+void bfmht_plan_destroy(bfmht_plan *plan);
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char *bfmht_last_error(void);
+
+/* Library version string. */
+const char *bfmht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFMHT_H */

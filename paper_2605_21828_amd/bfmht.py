@@ -1,0 +1,213 @@
+"""ctypes binding of libbfmht.so (the C ABI declared in include/bfmht.h).
+
+Argument marshalling only: every step of the apply runs in the HIP library.
+The raw entry points keep the C names (bfmht_plan_create, bfmht_apply, ...);
+`Plan` wraps them with PyTorch tensors for device memory and streams.  The
+library must have been built (python -m paper_2605_21828_amd.build); importing
+this module on a machine without it raises immediately, and a Plan refuses to
+run without a HIP device.  There is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfmht.so")
+
+F64, F32, BF16X2, BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x2": BF16X2, "bf16x3": BF16X3}
+OK, EINVAL, ESTATE, ENOSPACE, EHIP = 0, 1, 2, 3, 4
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOSPACE", 4: "EHIP"}
+
+
+class bfmht_factors_host(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("L", ctypes.c_int32),
+        ("perm_x", ctypes.c_void_p), ("xoff", ctypes.c_void_p), ("koff", ctypes.c_void_p),
+        ("rank", ctypes.c_void_p), ("ident", ctypes.c_void_p),
+        ("P", ctypes.c_void_p), ("P_off", ctypes.c_void_p), ("P_len", ctypes.c_int64),
+        ("U", ctypes.c_void_p), ("U_off", ctypes.c_void_p), ("U_len", ctypes.c_int64),
+    ]
+
+
+EXPORTED = [
+    "bfmht_plan_create", "bfmht_plan_device_bytes", "bfmht_workspace_bytes", "bfmht_plan_upload",
+    "bfmht_apply", "bfmht_apply_transpose", "bfmht_plan_destroy", "bfmht_last_error", "bfmht_version",
+]
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError("libbfmht.so not built: run `python -m paper_2605_21828_amd.build` (%s)" % path)
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.bfmht_plan_create.argtypes = [ctypes.POINTER(bfmht_factors_host), ctypes.c_int, i32, ctypes.POINTER(vp)]
+    lib.bfmht_plan_create.restype = ctypes.c_int
+    lib.bfmht_plan_device_bytes.argtypes = [vp]
+    lib.bfmht_plan_device_bytes.restype = i64
+    lib.bfmht_workspace_bytes.argtypes = [vp, i32]
+    lib.bfmht_workspace_bytes.restype = i64
+    lib.bfmht_plan_upload.argtypes = [vp, vp, i64, vp]
+    lib.bfmht_plan_upload.restype = ctypes.c_int
+    lib.bfmht_apply.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.bfmht_apply.restype = ctypes.c_int
+    lib.bfmht_apply_transpose.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.bfmht_apply_transpose.restype = ctypes.c_int
+    lib.bfmht_plan_destroy.argtypes = [vp]
+    lib.bfmht_plan_destroy.restype = None
+    lib.bfmht_last_error.argtypes = []
+    lib.bfmht_last_error.restype = ctypes.c_char_p
+    lib.bfmht_version.argtypes = []
+    lib.bfmht_version.restype = ctypes.c_char_p
+    return lib
+
+
+lib = load_library()
+
+
+class BfmhtError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib.bfmht_last_error().decode()
+        super().__init__("%s failed: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _check(status, where):
+    if status != OK:
+        raise BfmhtError(status, where)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def factors_struct(fs):
+    """Build the C struct from a factor-set dict; returns (struct, keepalive list)."""
+    keep = dict(
+        perm_x=_c(fs["perm_x"], np.int32), xoff=_c(fs["xoff"], np.int64), koff=_c(fs["koff"], np.int64),
+        rank=_c(fs["rank"], np.int32).ravel(), ident=_c(fs["ident"], np.uint8).ravel(),
+        P=_c(fs["P"], np.float64), P_off=_c(fs["P_off"], np.int64).ravel(),
+        U=_c(fs["U"], np.float64), U_off=_c(fs["U_off"], np.int64),
+    )
+    st = bfmht_factors_host()
+    st.n, st.m, st.L = int(fs["n"]), int(fs["m"]), int(fs["L"])
+    for k in ("perm_x", "xoff", "koff", "rank", "ident", "P", "P_off", "U", "U_off"):
+        setattr(st, k, keep[k].ctypes.data if keep[k].size else None)
+    st.P_len, st.U_len = keep["P"].size, keep["U"].size
+    return st, keep
+
+
+def bfmht_plan_create(fs, precision, max_nrhs=1):
+    """Returns an opaque plan handle (int) or raises BfmhtError."""
+    st, keep = factors_struct(fs)
+    h = ctypes.c_void_p()
+    _check(lib.bfmht_plan_create(ctypes.byref(st), int(precision), int(max_nrhs), ctypes.byref(h)),
+           "bfmht_plan_create")
+    del keep
+    return h.value
+
+
+def bfmht_plan_device_bytes(plan):
+    return lib.bfmht_plan_device_bytes(plan)
+
+
+def bfmht_workspace_bytes(plan, nrhs):
+    return lib.bfmht_workspace_bytes(plan, int(nrhs))
+
+
+def bfmht_plan_upload(plan, dev_ptr, dev_bytes, stream=0):
+    _check(lib.bfmht_plan_upload(plan, dev_ptr, int(dev_bytes), stream), "bfmht_plan_upload")
+
+
+def bfmht_apply(plan, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream=0):
+    _check(lib.bfmht_apply(plan, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream), "bfmht_apply")
+
+
+def bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream=0):
+    _check(lib.bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream),
+           "bfmht_apply_transpose")
+
+
+def bfmht_plan_destroy(plan):
+    lib.bfmht_plan_destroy(plan)
+
+
+class Plan:
+    """A factor set uploaded to one GPU in one precision.
+
+    apply(c)   -> f = Phi~ c      c: (m,) or (m, b) tensor on the plan's device
+    apply_t(f) -> g = Phi~^T f    f: (n,) or (n, b)
+    Element type: float64 for precision "f64", float32 otherwise.
+    Calls run on the current torch stream of the plan's device.
+    """
+
+    def __init__(self, fs, precision="f32", max_nrhs=64, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("bfmht.Plan needs a HIP device; there is no CPU path")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.precision = precision
+        self.dtype = torch.float64 if self.prec == F64 else torch.float32
+        self.n, self.m, self.L = int(fs["n"]), int(fs["m"]), int(fs["L"])
+        self.handle = bfmht_plan_create(fs, self.prec, max_nrhs)
+        nbytes = bfmht_plan_device_bytes(self.handle)
+        self._dev = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._dev.data_ptr()
+        self._dev_ptr = (base + 255) // 256 * 256
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            bfmht_plan_upload(self.handle, self._dev_ptr, nbytes, stream)
+        self.device_bytes = nbytes
+        self._ws = None
+        self._ws_ptr = 0
+        self._ws_bytes = 0
+
+    def workspace(self, nrhs):
+        need = bfmht_workspace_bytes(self.handle, nrhs)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = self.torch.empty(need + 256, dtype=self.torch.uint8, device=self.device)
+            self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+            self._ws_bytes = need
+        return self._ws_ptr, self._ws_bytes
+
+    def _prep(self, x, rows):
+        torch = self.torch
+        if x.device != self.device or x.dtype != self.dtype:
+            raise ValueError("expected a %s tensor on %s, got %s on %s" % (self.dtype, self.device, x.dtype, x.device))
+        squeeze = x.dim() == 1
+        if squeeze:
+            x = x.unsqueeze(1)
+        if x.dim() != 2 or x.shape[0] != rows:
+            raise ValueError("expected %d rows, got shape %s" % (rows, tuple(x.shape)))
+        if x.stride(1) != 1:
+            x = x.contiguous()
+        return x, squeeze
+
+    def apply(self, c, out=None):
+        torch = self.torch
+        c, squeeze = self._prep(c, self.m)
+        b = c.shape[1]
+        f = out if out is not None else torch.empty((self.n, b), dtype=self.dtype, device=self.device)
+        ws, wsb = self.workspace(b)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_apply(self.handle, c.data_ptr(), c.stride(0), f.data_ptr(), f.stride(0), b, ws, wsb, stream)
+        return f[:, 0] if squeeze else f
+
+    def apply_t(self, f, out=None):
+        torch = self.torch
+        f, squeeze = self._prep(f, self.n)
+        b = f.shape[1]
+        g = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        ws, wsb = self.workspace(b)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_apply_transpose(self.handle, f.data_ptr(), f.stride(0), g.data_ptr(), g.stride(0), b, ws, wsb, stream)
+        return g[:, 0] if squeeze else g
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            bfmht_plan_destroy(h)
+            self.handle = None

@@ -1,0 +1,470 @@
+// Host side of the C ABI: factor validation, device layout, upload and stage dispatch.
+//
+// The factor set (Sec. 2, the set returned by the butterfly factorization) is
+// laid out on the device as one pool of factor blocks in the plan's precision,
+// each block row-major with its row stride rounded up to 8 elements (zero
+// padded, so every row starts 16-byte aligned for any element type), followed
+// by the job and tile tables of every stage and the space-tree permutation.
+// Level vectors live in two caller-provided ping-pong buffers, row-major with
+// ld = nrhs, blocks in space-major order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bfmht.h"
+#include "bfmht_internal.h"
+
+using namespace bfmht;
+
+namespace {
+
+thread_local std::string g_err;
+
+bfmht_status fail(bfmht_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+int32_t ldw_of(int64_t k) { return (int32_t)align_up(k, 8); }
+
+uint16_t f32_to_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+struct StageDesc {
+  int kind;   // 0: level 0 (reads c), 1: transfer level, 2: final (writes f through perm_x)
+  int level;
+  int64_t fjob0, nfjob, ftile0, nftile;
+  int64_t bjob0, nbjob, btile0, nbtile;
+};
+
+}  // namespace
+
+struct bfmht_plan {
+  int prec = 0;
+  int64_t n = 0, m = 0;
+  int L = 0;
+  int32_t max_nrhs = 1;
+  int64_t esz = 0;       // bytes per element of level buffers and I/O
+  int64_t wsz = 0;       // bytes per element of the factor pool (per term for BF16)
+  int nterms = 1;        // 1, or 2 / 3 BF16 terms
+  std::vector<StageDesc> stages;
+  std::vector<int64_t> level_rows;
+  int64_t max_rows = 0;
+  int64_t pool_elems = 0;
+  int64_t stored_entries = 0;  // factor entries that are read once per apply (no padding)
+  int64_t off_pool[3] = {0, 0, 0};
+  int64_t off_fjobs = 0, off_bjobs = 0, off_tiles = 0, off_perm = 0, dev_bytes = 0;
+  std::vector<unsigned char> staging;
+  char *dev = nullptr;
+  bool uploaded = false;
+};
+
+namespace {
+
+bfmht_status validate(const bfmht_factors_host *f) {
+  if (!f) return fail(BFMHT_EINVAL, "factors is NULL");
+  if (f->n < 0 || f->m < 0) return fail(BFMHT_EINVAL, "negative n or m");
+  if (f->n >= (1ll << 31) || f->m >= (1ll << 31)) return fail(BFMHT_EINVAL, "n or m exceeds 2^31-1");
+  if (f->L < 0 || f->L > 24) return fail(BFMHT_EINVAL, "L out of range [0, 24]");
+  const int64_t nb = 1ll << f->L;
+  if (!f->xoff || !f->koff || !f->rank || !f->ident || !f->P_off || !f->U_off || (f->n > 0 && !f->perm_x))
+    return fail(BFMHT_EINVAL, "a required factor array is NULL");
+  if (f->xoff[0] != 0 || f->xoff[nb] != f->n) return fail(BFMHT_EINVAL, "xoff must run from 0 to n");
+  if (f->koff[0] != 0 || f->koff[nb] != f->m) return fail(BFMHT_EINVAL, "koff must run from 0 to m");
+  for (int64_t i = 0; i < nb; ++i) {
+    if (f->xoff[i + 1] < f->xoff[i]) return fail(BFMHT_EINVAL, "xoff not non-decreasing");
+    if (f->koff[i + 1] < f->koff[i]) return fail(BFMHT_EINVAL, "koff not non-decreasing");
+  }
+  std::vector<unsigned char> seen(f->n, 0);
+  for (int64_t t = 0; t < f->n; ++t) {
+    const int64_t p = f->perm_x[t];
+    if (p < 0 || p >= f->n || seen[p]) return fail(BFMHT_EINVAL, "perm_x is not a permutation of [0, n)");
+    seen[p] = 1;
+  }
+  for (int lvl = 0; lvl <= f->L; ++lvl) {
+    const int64_t nf = 1ll << (f->L - lvl);
+    for (int64_t q = 0; q < nb; ++q) {
+      const int64_t r = f->rank[lvl * nb + q];
+      int64_t rin;
+      if (lvl == 0) {
+        rin = f->koff[q + 1] - f->koff[q];
+      } else {
+        const int64_t i = q / nf, j = q % nf, p = i >> 1;
+        const int64_t q1 = p * 2 * nf + 2 * j;
+        rin = (int64_t)f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1];
+      }
+      if (r < 0 || r > rin)
+        return fail(BFMHT_EINVAL, "rank out of range at level " + std::to_string(lvl) + " block " + std::to_string(q));
+      if (f->ident[lvl * nb + q]) {
+        if (r != rin) return fail(BFMHT_EINVAL, "identity block whose rank differs from its input rows");
+      } else if (r > 0 && rin > 0) {
+        const int64_t o = f->P_off[lvl * nb + q];
+        if (!f->P || o < 0 || o + r * rin > f->P_len)
+          return fail(BFMHT_EINVAL, "P_off out of bounds at level " + std::to_string(lvl) + " block " + std::to_string(q));
+      }
+    }
+  }
+  for (int64_t i = 0; i < nb; ++i) {
+    const int64_t rows = f->xoff[i + 1] - f->xoff[i];
+    const int64_t r = f->rank[f->L * nb + i];
+    const int64_t o = f->U_off[i];
+    if (rows * r > 0 && (!f->U || o < 0 || o + rows * r > f->U_len))
+      return fail(BFMHT_EINVAL, "U_off out of bounds at leaf " + std::to_string(i));
+  }
+  return BFMHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bfmht_last_error(void) { return g_err.c_str(); }
+const char *bfmht_version(void) { return "bfmht 0.1 gfx950"; }
+
+bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs,
+                               bfmht_plan **out) {
+  if (!out) return fail(BFMHT_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (prec < BFMHT_F64 || prec > BFMHT_BF16X3) return fail(BFMHT_EINVAL, "unknown precision");
+  if (max_nrhs < 1) return fail(BFMHT_EINVAL, "max_nrhs must be >= 1");
+  bfmht_status st = validate(f);
+  if (st != BFMHT_OK) return st;
+
+  bfmht_plan *p = new bfmht_plan();
+  p->prec = prec;
+  p->n = f->n;
+  p->m = f->m;
+  p->L = f->L;
+  p->max_nrhs = max_nrhs;
+  p->esz = prec == BFMHT_F64 ? 8 : 4;
+  p->wsz = prec == BFMHT_F64 ? 8 : (prec == BFMHT_F32 ? 4 : 2);
+  p->nterms = prec == BFMHT_BF16X2 ? 2 : (prec == BFMHT_BF16X3 ? 3 : 1);
+  const int L = f->L;
+  const int64_t nb = 1ll << L;
+
+  // Row offsets of every block inside its level buffer (space-major order).
+  std::vector<std::vector<int64_t>> off(L + 1, std::vector<int64_t>(nb + 1, 0));
+  p->level_rows.assign(L + 1, 0);
+  for (int lvl = 0; lvl <= L; ++lvl) {
+    for (int64_t q = 0; q < nb; ++q) off[lvl][q + 1] = off[lvl][q] + f->rank[lvl * nb + q];
+    p->level_rows[lvl] = off[lvl][nb];
+    if (off[lvl][nb] >= (1ll << 31)) {
+      delete p;
+      return fail(BFMHT_EINVAL, "level vector exceeds 2^31 rows");
+    }
+    p->max_rows = std::max(p->max_rows, off[lvl][nb]);
+  }
+
+  // Pool offsets of every stored block.
+  struct Src { const double *ptr; int64_t rows, cols; };
+  std::vector<Src> blocks;
+  std::vector<int64_t> woff_P((size_t)(L + 1) * nb, -1), woff_U(nb, -1);
+  int64_t pool = 0;
+  auto rin_of = [&](int lvl, int64_t q) -> int64_t {
+    if (lvl == 0) return f->koff[q + 1] - f->koff[q];
+    const int64_t nf = 1ll << (L - lvl), i = q / nf, j = q % nf, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
+    return (int64_t)f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1];
+  };
+  for (int lvl = 0; lvl <= L; ++lvl)
+    for (int64_t q = 0; q < nb; ++q) {
+      if (f->ident[lvl * nb + q]) continue;
+      const int64_t r = f->rank[lvl * nb + q], k = rin_of(lvl, q);
+      woff_P[lvl * nb + q] = pool;
+      blocks.push_back({r * k ? f->P + f->P_off[lvl * nb + q] : nullptr, r, k});
+      pool += r * ldw_of(k);
+      p->stored_entries += r * k;
+    }
+  for (int64_t i = 0; i < nb; ++i) {
+    const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
+    woff_U[i] = pool;
+    blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r});
+    pool += rows * ldw_of(r);
+    p->stored_entries += rows * r;
+  }
+  p->pool_elems = pool;
+
+  // Stage tables.
+  std::vector<FwdJob> fj;
+  std::vector<BwdJob> bj;
+  std::vector<Tile> tiles;
+  const int BM = tile_rows(prec, max_nrhs);
+  auto add_ftiles = [&](StageDesc &s) {
+    s.ftile0 = (int64_t)tiles.size();
+    for (int64_t t = s.fjob0; t < s.fjob0 + s.nfjob; ++t)
+      for (int32_t m0 = 0; m0 < fj[t].M; m0 += BM) tiles.push_back({(int32_t)(t - s.fjob0), m0});
+    s.nftile = (int64_t)tiles.size() - s.ftile0;
+  };
+  auto add_btiles = [&](StageDesc &s) {
+    s.btile0 = (int64_t)tiles.size();
+    for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t)
+      for (int32_t m0 = 0; m0 < bj[t].K; m0 += BM) tiles.push_back({(int32_t)(t - s.bjob0), m0});
+    s.nbtile = (int64_t)tiles.size() - s.btile0;
+  };
+  auto cons_of = [&](int lvl, int64_t q) -> Cons {
+    Cons c;
+    const bool id = f->ident[lvl * nb + q] != 0;
+    c.w_off = id ? -1 : woff_P[lvl * nb + q];
+    c.M = f->rank[lvl * nb + q];
+    c.ldw = ldw_of(rin_of(lvl, q));
+    c.g_row = (int32_t)off[lvl][q];
+    c.pad = 0;
+    return c;
+  };
+  for (int lvl = 0; lvl <= L + 1; ++lvl) {
+    StageDesc s{};
+    s.kind = lvl == 0 ? 0 : (lvl <= L ? 1 : 2);
+    s.level = lvl;
+    s.fjob0 = (int64_t)fj.size();
+    s.bjob0 = (int64_t)bj.size();
+    if (lvl == 0) {
+      for (int64_t j = 0; j < nb; ++j) {
+        const bool id = f->ident[j] != 0;
+        const int64_t k = f->koff[j + 1] - f->koff[j];
+        fj.push_back({id ? -1 : woff_P[j], f->rank[j], (int32_t)k, ldw_of(k), (int32_t)f->koff[j], (int32_t)off[0][j], 0});
+        BwdJob b{};
+        b.K = (int32_t)k;
+        b.out_row = (int32_t)f->koff[j];
+        b.nc = 1;
+        b.c[0] = cons_of(0, j);
+        bj.push_back(b);
+      }
+    } else if (lvl <= L) {
+      const int64_t nf = 1ll << (L - lvl);
+      for (int64_t i = 0; i < (1ll << lvl); ++i)
+        for (int64_t j = 0; j < nf; ++j) {
+          const int64_t q = i * nf + j, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
+          const bool id = f->ident[lvl * nb + q] != 0;
+          const int64_t k = rin_of(lvl, q);
+          fj.push_back({id ? -1 : woff_P[lvl * nb + q], f->rank[lvl * nb + q], (int32_t)k, ldw_of(k),
+                        (int32_t)off[lvl - 1][q1], (int32_t)off[lvl][q], 0});
+        }
+      for (int64_t pp = 0; pp < (1ll << (lvl - 1)); ++pp)
+        for (int64_t j = 0; j < nf; ++j) {
+          const int64_t q1 = pp * 2 * nf + 2 * j;
+          BwdJob b{};
+          b.K = (int32_t)(f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1]);
+          b.out_row = (int32_t)off[lvl - 1][q1];
+          b.nc = 2;
+          b.c[0] = cons_of(lvl, (2 * pp) * nf + j);
+          b.c[1] = cons_of(lvl, (2 * pp + 1) * nf + j);
+          bj.push_back(b);
+        }
+    } else {
+      for (int64_t i = 0; i < nb; ++i) {
+        const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
+        fj.push_back({woff_U[i], (int32_t)rows, (int32_t)r, ldw_of(r), (int32_t)off[L][i], (int32_t)f->xoff[i], 0});
+        BwdJob b{};
+        b.K = (int32_t)r;
+        b.out_row = (int32_t)off[L][i];
+        b.nc = 1;
+        b.c[0].w_off = woff_U[i];
+        b.c[0].M = (int32_t)rows;
+        b.c[0].ldw = ldw_of(r);
+        b.c[0].g_row = (int32_t)f->xoff[i];
+        bj.push_back(b);
+      }
+    }
+    s.nfjob = (int64_t)fj.size() - s.fjob0;
+    s.nbjob = (int64_t)bj.size() - s.bjob0;
+    p->stages.push_back(s);
+  }
+  for (auto &s : p->stages) {
+    add_ftiles(s);
+    add_btiles(s);
+  }
+
+  // Device layout.
+  int64_t cur = 0;
+  for (int t = 0; t < p->nterms; ++t) {
+    p->off_pool[t] = cur;
+    cur = align_up(cur + pool * p->wsz, 256);
+  }
+  p->off_fjobs = cur;
+  cur = align_up(cur + (int64_t)fj.size() * (int64_t)sizeof(FwdJob), 256);
+  p->off_bjobs = cur;
+  cur = align_up(cur + (int64_t)bj.size() * (int64_t)sizeof(BwdJob), 256);
+  p->off_tiles = cur;
+  cur = align_up(cur + (int64_t)tiles.size() * (int64_t)sizeof(Tile), 256);
+  p->off_perm = cur;
+  cur = align_up(cur + f->n * 4, 256);
+  p->dev_bytes = std::max<int64_t>(cur, 256);
+
+  try {
+    p->staging.assign((size_t)p->dev_bytes, 0);
+  } catch (...) {
+    delete p;
+    return fail(BFMHT_ENOSPACE, "host staging allocation failed");
+  }
+  unsigned char *S = p->staging.data();
+  int64_t bo = 0;
+  for (const Src &b : blocks) {
+    const int64_t ld = ldw_of(b.cols);
+    for (int64_t r = 0; r < b.rows; ++r)
+      for (int64_t c = 0; c < b.cols; ++c) {
+        const double x = b.ptr[r * b.cols + c];
+        const int64_t e = bo + r * ld + c;
+        if (prec == BFMHT_F64) {
+          reinterpret_cast<double *>(S + p->off_pool[0])[e] = x;
+        } else if (prec == BFMHT_F32) {
+          reinterpret_cast<float *>(S + p->off_pool[0])[e] = (float)x;
+        } else {
+          const float x32 = (float)x;
+          const uint16_t hi = f32_to_bf16(x32);
+          const float r1 = x32 - bf16_to_f32(hi);
+          const uint16_t lo = f32_to_bf16(r1);
+          reinterpret_cast<uint16_t *>(S + p->off_pool[0])[e] = hi;
+          reinterpret_cast<uint16_t *>(S + p->off_pool[1])[e] = lo;
+          if (p->nterms == 3)
+            reinterpret_cast<uint16_t *>(S + p->off_pool[2])[e] = f32_to_bf16(r1 - bf16_to_f32(lo));
+        }
+      }
+    bo += b.rows * ld;
+  }
+  if (!fj.empty()) std::memcpy(S + p->off_fjobs, fj.data(), fj.size() * sizeof(FwdJob));
+  if (!bj.empty()) std::memcpy(S + p->off_bjobs, bj.data(), bj.size() * sizeof(BwdJob));
+  if (!tiles.empty()) std::memcpy(S + p->off_tiles, tiles.data(), tiles.size() * sizeof(Tile));
+  if (f->n) std::memcpy(S + p->off_perm, f->perm_x, (size_t)f->n * 4);
+  *out = p;
+  return BFMHT_OK;
+}
+
+int64_t bfmht_plan_device_bytes(const bfmht_plan *p) { return p ? p->dev_bytes : -1; }
+
+int64_t bfmht_workspace_bytes(const bfmht_plan *p, int32_t nrhs) {
+  if (!p || nrhs < 0) return -1;
+  const int64_t one = align_up(p->max_rows * (int64_t)nrhs * p->esz, 256);
+  return std::max<int64_t>(2 * one, 256);
+}
+
+bfmht_status bfmht_plan_upload(bfmht_plan *p, void *dev_buf, int64_t dev_bytes, void *stream) {
+  if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
+  if (p->uploaded) return fail(BFMHT_ESTATE, "plan already uploaded");
+  if (!dev_buf) return fail(BFMHT_EINVAL, "dev_buf is NULL");
+  if (((uintptr_t)dev_buf) % 256) return fail(BFMHT_EINVAL, "dev_buf must be 256-byte aligned");
+  if (dev_bytes < p->dev_bytes) return fail(BFMHT_ENOSPACE, "dev_buf smaller than bfmht_plan_device_bytes");
+  hipError_t e = hipMemcpyAsync(dev_buf, p->staging.data(), (size_t)p->dev_bytes, hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("upload: ") + hipGetErrorString(e));
+  std::vector<unsigned char>().swap(p->staging);
+  p->dev = static_cast<char *>(dev_buf);
+  p->uploaded = true;
+  return BFMHT_OK;
+}
+
+void bfmht_plan_destroy(bfmht_plan *p) { delete p; }
+
+}  // extern "C"
+
+namespace {
+
+bfmht_status check_call(const bfmht_plan *p, const void *in, int64_t ldin, const void *out, int64_t ldout,
+                        int32_t nrhs, const void *ws, int64_t ws_bytes) {
+  if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
+  if (!p->uploaded) return fail(BFMHT_ESTATE, "plan not uploaded");
+  if (nrhs < 0) return fail(BFMHT_EINVAL, "nrhs < 0");
+  if (nrhs == 0) return BFMHT_OK;
+  if (!in || !out || !ws) return fail(BFMHT_EINVAL, "NULL input, output or workspace");
+  if (ldin < nrhs || ldout < nrhs) return fail(BFMHT_EINVAL, "ld smaller than nrhs");
+  if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < bfmht_workspace_bytes(p, nrhs)) return fail(BFMHT_ENOSPACE, "workspace too small");
+  return BFMHT_OK;
+}
+
+StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
+  StageArgs a{};
+  a.pool = p->dev + p->off_pool[0];
+  a.pool_lo = p->nterms > 1 ? p->dev + p->off_pool[1] : nullptr;
+  a.pool_lo2 = p->nterms > 2 ? p->dev + p->off_pool[2] : nullptr;
+  if (fwd) {
+    a.jobs = p->dev + p->off_fjobs + s.fjob0 * (int64_t)sizeof(FwdJob);
+    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.ftile0;
+    a.ntiles = (int32_t)s.nftile;
+  } else {
+    a.jobs = p->dev + p->off_bjobs + s.bjob0 * (int64_t)sizeof(BwdJob);
+    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0;
+    a.ntiles = (int32_t)s.nbtile;
+  }
+  a.rowmap = s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *f, int64_t ldf, int32_t nrhs,
+                         void *ws, int64_t ws_bytes, void *stream) {
+  bfmht_status st = check_call(p, c, ldc, f, ldf, nrhs, ws, ws_bytes);
+  if (st != BFMHT_OK || nrhs == 0) return st;
+  char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + align_up(p->max_rows * (int64_t)nrhs * p->esz, 256)};
+  for (const StageDesc &s : p->stages) {
+    StageArgs a = base_args(p, s, true);
+    a.nrhs = nrhs;
+    if (s.kind == 0) {
+      a.src = c;
+      a.lds = ldc;
+    } else {
+      a.src = buf[(s.level - 1) & 1];
+      a.lds = nrhs;
+    }
+    if (s.kind == 2) {
+      a.dst = f;
+      a.ldd = ldf;
+    } else {
+      a.dst = buf[s.level & 1];
+      a.ldd = nrhs;
+    }
+    const int e = launch_fwd_stage(p->prec, a, stream);
+    if (e) return fail(BFMHT_EHIP, std::string("apply stage launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  return BFMHT_OK;
+}
+
+bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t ldf, void *g, int64_t ldg,
+                                   int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
+  bfmht_status st = check_call(p, f, ldf, g, ldg, nrhs, ws, ws_bytes);
+  if (st != BFMHT_OK || nrhs == 0) return st;
+  char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + align_up(p->max_rows * (int64_t)nrhs * p->esz, 256)};
+  for (auto it = p->stages.rbegin(); it != p->stages.rend(); ++it) {
+    const StageDesc &s = *it;
+    StageArgs a = base_args(p, s, false);
+    a.nrhs = nrhs;
+    // transposed stage at forward level l writes the level l-1 vector (or g)
+    if (s.kind == 2) {
+      a.src = f;
+      a.lds = ldf;
+    } else {
+      a.src = buf[s.level & 1];
+      a.lds = nrhs;
+    }
+    if (s.kind == 0) {
+      a.dst = g;
+      a.ldd = ldg;
+    } else {
+      a.dst = buf[(s.level - 1) & 1];
+      a.ldd = nrhs;
+    }
+    const int e = launch_bwd_stage(p->prec, a, stream);
+    if (e) return fail(BFMHT_EHIP, std::string("apply_transpose stage launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  return BFMHT_OK;
+}
+
+}  // extern "C"

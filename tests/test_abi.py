@@ -1,0 +1,117 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad factor sets and calls with the documented status."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from factor_gen import random_factor_set
+from paper_2605_21828_amd import bfmht as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bfmht.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bfmht_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    syms = declared_symbols()
+    assert "bfmht_apply" in syms and "bfmht_apply_transpose" in syms
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) <= set(B.EXPORTED)
+
+
+def test_struct_layout_matches_header_order():
+    names = [f[0] for f in B.bfmht_factors_host._fields_]
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {"):text.index("} bfmht_factors_host;")]
+    hdr = re.findall(r"\*?\s*(\w+)(?:,\s*(\w+))?;", body)
+    flat = []
+    for a, b in hdr:
+        flat.append(a)
+        if b:
+            flat.append(b)
+    assert flat == names
+
+
+@pytest.fixture(scope="module")
+def good():
+    return random_factor_set(3, 60, 40, 3, max_rank=8)
+
+
+def test_plan_create_sizes(good):
+    for prec in (B.F64, B.F32, B.BF16X2, B.BF16X3):
+        h = B.bfmht_plan_create(good, prec, 4)
+        assert B.bfmht_plan_device_bytes(h) > 0
+        w1, w8 = B.bfmht_workspace_bytes(h, 1), B.bfmht_workspace_bytes(h, 8)
+        assert 0 < w1 <= w8
+        assert B.bfmht_workspace_bytes(h, -1) == -1
+        B.bfmht_plan_destroy(h)
+
+
+def _expect(fs, status, prec=B.F32, max_nrhs=1):
+    with pytest.raises(B.BfmhtError) as e:
+        B.bfmht_plan_create(fs, prec, max_nrhs)
+    assert e.value.status == status
+
+
+def test_rejects_bad_permutation(good):
+    bad = dict(good, perm_x=good["perm_x"].copy())
+    bad["perm_x"][0] = bad["perm_x"][1]
+    _expect(bad, B.EINVAL)
+
+
+def test_rejects_bad_offsets(good):
+    bad = dict(good, xoff=good["xoff"].copy())
+    bad["xoff"][-1] += 1
+    _expect(bad, B.EINVAL)
+    bad = dict(good, koff=good["koff"][::-1].copy())
+    _expect(bad, B.EINVAL)
+
+
+def test_rejects_rank_above_inputs(good):
+    bad = dict(good, rank=good["rank"].copy())
+    bad["rank"][0, 0] = good["koff"][1] - good["koff"][0] + 1
+    _expect(bad, B.EINVAL)
+
+
+def test_rejects_out_of_bounds_block(good):
+    bad = dict(good, P_off=good["P_off"].copy())
+    q = np.argwhere((good["ident"] == 0) & (good["rank"] > 0))[0]
+    bad["P_off"][q[0], q[1]] = good["P"].size
+    _expect(bad, B.EINVAL)
+    bad = dict(good, U=good["U"][:-1].copy())
+    if good["U"].size:
+        _expect(bad, B.EINVAL)
+
+
+def test_rejects_bad_arguments(good):
+    _expect(good, B.EINVAL, prec=7)
+    _expect(good, B.EINVAL, max_nrhs=0)
+    h = ctypes.c_void_p()
+    assert B.lib.bfmht_plan_create(None, 0, 1, ctypes.byref(h)) == B.EINVAL
+    assert h.value is None
+
+
+def test_apply_before_upload_is_state_error(good):
+    h = B.bfmht_plan_create(good, B.F32, 1)
+    try:
+        st = B.lib.bfmht_apply(h, 1 << 20, 1, 1 << 21, 1, 1, 1 << 22, 1 << 20, None)
+        assert st == B.ESTATE
+        st = B.lib.bfmht_apply_transpose(h, 1 << 20, 1, 1 << 21, 1, 1, 1 << 22, 1 << 20, None)
+        assert st == B.ESTATE
+        assert b"not uploaded" in B.lib.bfmht_last_error()
+    finally:
+        B.bfmht_plan_destroy(h)
+
+
+def test_destroy_null_is_noop():
+    B.lib.bfmht_plan_destroy(None)
+    assert B.lib.bfmht_version().startswith(b"bfmht")
