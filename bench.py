@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -100,7 +101,7 @@ def main():
     n, m, b = w["n"], w["m"], w["nrhs"]
     pts = wl.points_for(w)
     log("building factors: n=%d m=%d leaf=%d tol=%g" % (n, m, w["leaf"], w["tol"]))
-    fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=False,
+    fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
                                 log=lambda s: log("  factor", s))
     F = fio.stored_entries(fs)
     modes = real_modes(m)
@@ -147,7 +148,6 @@ def main():
 
     if not args.no_f64:
         log("uploading FP64 plan")
-        del_fp = None
         p64 = Plan(fs, "f64", max_nrhs=b, device=dev)
         c64 = torch.tensor(c_host, dtype=torch.float64, device=dev)
         f64 = torch.tensor(f_host, dtype=torch.float64, device=dev)
@@ -165,7 +165,7 @@ def main():
             "speedup_fp32_vs_fp64_plain": (ms64_fwd + ms64_bwd) / (ms_fwd + ms_bwd),
             "fp32_vs_fp64_gpu_rel_err": rel,
         })
-        del p64, c64, f64, y64, g64, d32, del_fp
+        del p64, c64, f64, y64, g64, d32
         torch.cuda.empty_cache()
 
     base = None

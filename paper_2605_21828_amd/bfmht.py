@@ -147,7 +147,10 @@ class Plan:
         if not torch.cuda.is_available():
             raise RuntimeError("bfmht.Plan needs a HIP device; there is no CPU path")
         self.torch = torch
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
         self.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.precision = precision
         self.dtype = torch.float64 if self.prec == F64 else torch.float32

@@ -26,6 +26,12 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Row of accumulator register i of `lane` inside a 16x16 MFMA output tile (the
+// column is lane % 16).  The FP32 form stacks registers inside a lane group;
+// the FP64 form interleaves lane groups across registers.
+__device__ __forceinline__ int acc_row(float, int lane, int i) { return 4 * (lane >> 4) + i; }
+__device__ __forceinline__ int acc_row(double, int lane, int i) { return 4 * i + (lane >> 4); }
+
 constexpr int kBM = 64;   // output rows per workgroup
 constexpr int kBK = 16;   // reduction depth staged per LDS round
 constexpr int kNT = 256;  // threads per workgroup
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
     for (int fn = 0; fn < Lt::FN; ++fn)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + 4 * (lane >> 4) + i;
+        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + acc_row(T(0), lane, i);
         const int gc = n0 + wn * Lt::TN + fn * 16 + (lane & 15);
         if (gr < J.M && gc < a.nrhs) dst[map_row(a.rowmap, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
       }
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
     for (int fn = 0; fn < Lt::FN; ++fn)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + 4 * (lane >> 4) + i;
+        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + acc_row(T(0), lane, i);
         const int gc = n0 + wn * Lt::TN + fn * 16 + (lane & 15);
         if (gr < J.K && gc < a.nrhs) {
           T v = acc[fm][fn][i];
