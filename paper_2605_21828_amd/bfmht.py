@@ -11,6 +11,11 @@ import ctypes
 import os
 
 import numpy as np
+# PyTorch carries its own HIP runtime (soname libamdhip64.so.7).  Importing it
+# before the library is loaded makes the library's libamdhip64 dependency
+# resolve to that same runtime, so one HIP runtime owns the device, the
+# streams and the memory in the process.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfmht.so")

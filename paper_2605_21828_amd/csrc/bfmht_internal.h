@@ -1,14 +1,18 @@
 // Internal layout shared by the host plan (plan.cpp) and the HIP kernels (kernels.hip).
 //
 // An apply is a sequence of stages.  Each stage is a grouped GEMM over jobs of
-// uneven size; every job reads a contiguous run of rows of its source buffer
-// and writes rows of its destination buffer.
-//   forward stage 0      : y_0[q]       = P_0j   c[koff[j] ..]          (src = c)
-//   forward stage l=1..L : y_l[q]       = P_lq   y_{l-1}[pair rows]     (level buffers)
-//   forward final stage  : f[perm_x[..]] = U_i    y_L[i]                 (dst = f, row map)
+// uneven size; every job reads rows of its source buffer and writes rows of its
+// destination buffer.
+//   forward stage 0      : y_0[q]        = P_0j  c[koff[j] ..]          (src = c)
+//   forward stage l=1..L : y_l[q]        = P_lq  y_{l-1}[pair rows]     (level buffers)
+//   forward final stage  : f[perm_x[..]] = U_i   y_L[i]                 (dst = f, row map)
 // The transposed stages run in reverse; a transposed job owns one contiguous
 // run of output rows (the pair of input blocks of a forward level) and sums the
 // transposed products of its consumers, so no two jobs write the same row.
+//
+// Factor blocks are stored twice: row-major W (M x K, row stride ldw) for the
+// forward stages and row-major W^T (K x M, row stride ldwt) for the transposed
+// stages, so both directions stream factor rows with the same access pattern.
 #pragma once
 #include <stdint.h>
 
@@ -16,7 +20,7 @@ namespace bfmht {
 
 // One forward GEMM job: dst rows = W (M x K, row stride ldw) * src rows.
 struct FwdJob {
-  int64_t w_off;   // element offset of W in the factor pool; -1 = identity (copy)
+  int64_t w_off;   // element offset of W in the forward pool; -1 = identity (copy)
   int32_t M;       // output rows
   int32_t K;       // input rows
   int32_t ldw;     // row stride of W in elements (K rounded up to 8)
@@ -25,12 +29,12 @@ struct FwdJob {
   int32_t pad;
 };
 
-// One consumer of a transposed job: its forward block W (M x K) and where the
-// incoming gradient rows live.
+// One consumer of a transposed job: the transposed copy of its forward block
+// (W^T, K x M) and where the incoming gradient rows live.
 struct Cons {
-  int64_t w_off;   // -1 = identity consumer (its gradient rows are added as is)
-  int32_t M;       // rows of W = gradient rows read
-  int32_t ldw;
+  int64_t wt_off;  // element offset of W^T in the transposed pool; -1 = identity consumer
+  int32_t M;       // columns of W^T = gradient rows read
+  int32_t ldwt;    // row stride of W^T (M rounded up to 8)
   int32_t g_row;   // first gradient row (or row-map index when the stage has a row map)
   int32_t pad;
 };
@@ -53,12 +57,13 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X2 = 2, P_BF16X3 = 3 };
 
 // Everything a stage launch needs, device pointers resolved.
 struct StageArgs {
-  const void *pool;       // factor pool (element type per precision; BF16: hi terms)
+  const void *pool;       // factor pool of this direction (BF16: hi terms)
   const void *pool_lo;    // BF16 only: lo terms (same offsets)
   const void *pool_lo2;   // BF16X3 only: lo2 terms
   const void *jobs;       // FwdJob* or BwdJob*
   const Tile *tiles;
   int32_t ntiles;
+  int32_t vec;            // 1 when src rows may be read with 16-byte vector loads
   const void *src;
   int64_t lds;
   void *dst;
@@ -67,9 +72,8 @@ struct StageArgs {
   int32_t nrhs;
 };
 
-// Tile height (rows of output per workgroup) used by the kernels for a precision
-// and nrhs; the plan builds its tile lists for these heights.
-int tile_rows(int prec, int nrhs);
+// Output rows per workgroup tile; the plan builds its tile lists for this height.
+constexpr int kTileRows = 64;
 
 // Launch one stage.  Returns 0 or a hipError_t value.
 int launch_fwd_stage(int prec, const StageArgs &a, void *stream);

@@ -2,10 +2,21 @@
 //
 // Every stage is a batch of small dense products of uneven size (Sec. 2: the
 // level-0 bases, the transfer blocks of levels 1..L and the leaf column bases
-// are each applied once per vector; storage and apply cost coincide, Sec. 7.2).
-// One workgroup (4 waves of 64 lanes) computes a BM x BN tile of one job's
-// output; factor rows and right-hand-side rows are staged through LDS and fed to
-// 16x16 MFMA tiles with FP32 (or FP64) accumulation.
+// are each applied once per vector, which is why storage and apply cost
+// coincide, Sec. 7.2).
+//
+// Work split.  A workgroup of 4 waves computes a 64-row x BN-column output tile
+// of one job; each wave owns 16 rows and all BN columns, so every factor element
+// is used by exactly one wave.  Factor rows therefore go straight from HBM into
+// MFMA operand registers (no LDS round trip): per reduction chunk a lane loads
+// 32 contiguous bytes of its row, and the four lane groups together cover one
+// 128-byte line per row.  The reduction index is permuted inside a chunk (lane
+// group g and step t take k = KL*g + t), which is legal because both operands
+// use the same permutation.  The right-hand-side chunk (KC rows x BN columns) is
+// shared by the 4 waves and staged through LDS, transposed so that each lane
+// reads its KL consecutive k values with 16-byte LDS reads.  LDS is double
+// buffered: the loads of chunk c+1 are in flight while chunk c runs on the
+// matrix cores, with one barrier per chunk.
 #include <hip/hip_runtime.h>
 
 #include "bfmht_internal.h"
@@ -15,9 +26,15 @@ namespace bfmht {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Acc4;
-template <> struct Acc4<float> { typedef v4f type; };
-template <> struct Acc4<double> { typedef v4d type; };
+template <typename T> struct Cfg;
+template <> struct Cfg<float> {
+  static constexpr int KC = 32;  // reduction depth per chunk
+  typedef v4f acc_t;
+};
+template <> struct Cfg<double> {
+  static constexpr int KC = 16;
+  typedef v4d acc_t;
+};
 
 __device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -32,54 +49,132 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
 __device__ __forceinline__ int acc_row(float, int lane, int i) { return 4 * (lane >> 4) + i; }
 __device__ __forceinline__ int acc_row(double, int lane, int i) { return 4 * i + (lane >> 4); }
 
-constexpr int kBM = 64;   // output rows per workgroup
-constexpr int kBK = 16;   // reduction depth staged per LDS round
-constexpr int kNT = 256;  // threads per workgroup
+constexpr int kWaves = 4;
+constexpr int kNT = 64 * kWaves;
+static_assert(kTileRows == 16 * kWaves, "one 16-row MFMA block per wave");
 
-int tile_rows(int /*prec*/, int /*nrhs*/) { return kBM; }
-
-// Wave layout inside a BM x BN tile: WN waves across columns, 4/WN down rows.
-template <int BN> struct Layout {
-  static constexpr int WN = BN >= 64 ? 2 : 1;
-  static constexpr int WM = 4 / WN;
-  static constexpr int TM = kBM / WM;  // rows per wave
-  static constexpr int TN = BN / WN;   // columns per wave
-  static constexpr int FM = TM / 16;   // 16x16 MFMA blocks per wave
-  static constexpr int FN = TN / 16;
-};
-
-// Source row of the t-th row of a job, through the stage row map if present.
-__device__ __forceinline__ int64_t map_row(const int32_t *rowmap, int32_t base, int32_t t) {
-  return rowmap ? (int64_t)rowmap[base + t] : (int64_t)(base + t);
+// Copy N elements (N * sizeof(T) a multiple of 8 bytes) with 16- or 8-byte accesses.
+template <typename T, int N>
+__device__ __forceinline__ void copy_vec(T *dst, const T *src) {
+  constexpr int bytes = N * (int)sizeof(T);
+  if constexpr (bytes % 16 == 0) {
+#pragma unroll
+    for (int i = 0; i < bytes / 16; ++i) reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(src)[i];
+  } else {
+    static_assert(bytes % 8 == 0, "vector copy granularity");
+#pragma unroll
+    for (int i = 0; i < bytes / 8; ++i) reinterpret_cast<uint2 *>(dst)[i] = reinterpret_cast<const uint2 *>(src)[i];
+  }
 }
 
-// Inner product over one LDS round: acc += A_lds(rows of this wave) * B_lds(cols).
 template <typename T, int BN>
-__device__ __forceinline__ void mma_round(const T (*As)[kBK + 1], const T (*Bs)[BN + 1],
-                                          typename Acc4<T>::type (&acc)[Layout<BN>::FM][Layout<BN>::FN],
-                                          int wm, int wn, int lane) {
-  typedef Layout<BN> Lt;
+struct Tiling {
+  static constexpr int KC = Cfg<T>::KC;
+  static constexpr int KL = KC / 4;                 // reduction values per lane per chunk
+  static constexpr int FN = BN / 16;                // 16-column MFMA blocks per wave
+  static constexpr int XPAD = 16 / (int)sizeof(T);  // 16-byte row padding of the LDS chunk
+  static constexpr int XR = KC * BN / kNT;          // RHS values staged per thread per chunk
+  static constexpr int XS = KC + XPAD;              // LDS row stride (elements) of the transposed chunk
+  static constexpr int XBUF = BN * XS;              // elements per LDS buffer
+  static_assert(XR >= 1 && BN % XR == 0, "staging split");
+};
+
+// Stage one RHS chunk: rows k0 .. k0+KC of a row-mapped source into registers.
+template <typename T, int BN>
+__device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t *rowmap, int32_t base, int32_t nrows,
+                                       int k0, int n0, int tid) {
+  typedef Tiling<T, BN> Tl;
+  const int e = tid * Tl::XR;
+  const int k = e / BN, c = e % BN;
+  const int gk = k0 + k;
 #pragma unroll
-  for (int kk = 0; kk < kBK; kk += 4) {
-    T a[Lt::FM], b[Lt::FN];
+  for (int i = 0; i < Tl::XR; ++i) xr[i] = T(0);
+  if (e >= Tl::KC * BN || gk >= nrows) return;
+  const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
+  const T *p = static_cast<const T *>(a.src) + srow * a.lds + n0 + c;
+  if (a.vec && n0 + c + Tl::XR <= a.nrhs) {
+    copy_vec<T, Tl::XR>(xr, p);
+  } else {
 #pragma unroll
-    for (int fm = 0; fm < Lt::FM; ++fm) a[fm] = As[wm * Lt::TM + fm * 16 + (lane & 15)][kk + (lane >> 4)];
+    for (int i = 0; i < Tl::XR; ++i)
+      if (n0 + c + i < a.nrhs) xr[i] = p[i];
+  }
+}
+
+template <typename T, int BN>
+__device__ __forceinline__ void store_x(T *Xs, const T *xr, int tid) {
+  typedef Tiling<T, BN> Tl;
+  const int e = tid * Tl::XR;
+  if (e >= Tl::KC * BN) return;
+  const int k = e / BN, c = e % BN;
 #pragma unroll
-    for (int fn = 0; fn < Lt::FN; ++fn) b[fn] = Bs[kk + (lane >> 4)][wn * Lt::TN + fn * 16 + (lane & 15)];
+  for (int i = 0; i < Tl::XR; ++i) Xs[(c + i) * Tl::XS + k] = xr[i];
+}
+
+// Load this lane's KL reduction values of factor row `wrow` for the chunk at k0.
+template <typename T, int BN>
+__device__ __forceinline__ void load_w(T *wr, const T *wrow, int ldw, int k0, int lg) {
+  typedef Tiling<T, BN> Tl;
+  const int k = k0 + Tl::KL * lg;
+  if (k < ldw) {
+    copy_vec<T, Tl::KL>(wr, wrow + k);
+  } else {
 #pragma unroll
-    for (int fm = 0; fm < Lt::FM; ++fm)
+    for (int i = 0; i < Tl::KL; ++i) wr[i] = T(0);
+  }
+}
+
+// acc += W_chunk (this wave's 16 rows) * X_chunk (all BN columns).
+template <typename T, int BN>
+__device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t *acc, const T *wr, const T *Xs, int lrow, int lg) {
+  typedef Tiling<T, BN> Tl;
 #pragma unroll
-      for (int fn = 0; fn < Lt::FN; ++fn) acc[fm][fn] = mfma16x16x4(a[fm], b[fn], acc[fm][fn]);
+  for (int fn = 0; fn < Tl::FN; ++fn) {
+    T b[Tl::KL];
+    copy_vec<T, Tl::KL>(b, &Xs[(fn * 16 + lrow) * Tl::XS + Tl::KL * lg]);
+#pragma unroll
+    for (int t = 0; t < Tl::KL; ++t) acc[fn] = mfma16x16x4(wr[t], b[t], acc[fn]);
+  }
+}
+
+// Reduction over one factor block: acc += W(rows of this wave) * src rows.
+// W is row-major with stride ldw; the reduction runs over nk source rows read
+// through the optional row map starting at `base`.
+template <typename T, int BN>
+__device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t *acc, const T *wrow, int ldw, int nk,
+                                           const StageArgs &a, const int32_t *rowmap, int32_t base, int n0, T *Xs,
+                                           int tid, int lrow, int lg) {
+  typedef Tiling<T, BN> Tl;
+  const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
+  if (nchunk == 0) return;
+  T wA[Tl::KL], wB[Tl::KL], xB[Tl::XR];
+  load_w<T, BN>(wA, wrow, ldw, 0, lg);
+  load_x<T, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
+  store_x<T, BN>(Xs, xB, tid);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const bool more = c + 1 < nchunk;
+    if (more) {
+      load_w<T, BN>(wB, wrow, ldw, (c + 1) * Tl::KC, lg);
+      load_x<T, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
+    }
+    mma_chunk<T, BN>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    if (more) {
+      store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
+#pragma unroll
+      for (int i = 0; i < Tl::KL; ++i) wA[i] = wB[i];
+    }
+    __syncthreads();
   }
 }
 
 // Forward stage: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
 template <typename T, int BN>
 __global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
-  typedef Layout<BN> Lt;
-  __shared__ T As[kBM][kBK + 1];
-  __shared__ T Bs[kBK][BN + 1];
+  typedef Tiling<T, BN> Tl;
+  __shared__ __attribute__((aligned(16))) T Xs[2 * Tl::XBUF];
   const Tile tile = a.tiles[blockIdx.x];
+  if (tile.job < 0) return;  // padding tile of a short XCD bin
   const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
   const int n0 = blockIdx.y * BN;
   const T *src = static_cast<const T *>(a.src);
@@ -87,110 +182,81 @@ __global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
   const int tid = threadIdx.x;
 
   if (J.w_off < 0) {  // identity block: copy its rows
-    for (int e = tid; e < kBM * BN; e += kNT) {
+    for (int e = tid; e < kTileRows * BN; e += kNT) {
       const int r = e / BN, c = e % BN;
       const int gr = tile.m0 + r, gc = n0 + c;
-      if (gr < J.M && gc < a.nrhs)
-        dst[map_row(a.rowmap, J.out_row, gr) * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
+      if (gr < J.M && gc < a.nrhs) {
+        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
+        dst[drow * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
+      }
     }
     return;
   }
 
-  const T *W = static_cast<const T *>(a.pool) + J.w_off;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / Lt::WN, wn = wave % Lt::WN;
-  typename Acc4<T>::type acc[Lt::FM][Lt::FN];
+  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int row = tile.m0 + wave * 16 + lrow;  // factor row this lane streams
+  const T *wrow = static_cast<const T *>(a.pool) + J.w_off + (int64_t)min(row, J.M - 1) * J.ldw;
+  typename Cfg<T>::acc_t acc[Tl::FN];
 #pragma unroll
-  for (int i = 0; i < Lt::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < Lt::FN; ++j) acc[i][j] = typename Acc4<T>::type{0, 0, 0, 0};
-
-  for (int k0 = 0; k0 < J.K; k0 += kBK) {
-    for (int e = tid; e < kBM * kBK; e += kNT) {
-      const int r = e / kBK, k = e % kBK;
-      const int gr = tile.m0 + r, gk = k0 + k;
-      As[r][k] = (gr < J.M && gk < J.K) ? W[(int64_t)gr * J.ldw + gk] : T(0);
-    }
-    for (int e = tid; e < kBK * BN; e += kNT) {
-      const int k = e / BN, c = e % BN;
-      const int gk = k0 + k, gc = n0 + c;
-      Bs[k][c] = (gk < J.K && gc < a.nrhs) ? src[(int64_t)(J.in_row + gk) * a.lds + gc] : T(0);
-    }
-    __syncthreads();
-    mma_round<T, BN>(As, Bs, acc, wm, wn, lane);
-    __syncthreads();
-  }
+  for (int i = 0; i < Tl::FN; ++i) acc[i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
+  gemm_block<T, BN>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
 
 #pragma unroll
-  for (int fm = 0; fm < Lt::FM; ++fm)
+  for (int fn = 0; fn < Tl::FN; ++fn)
 #pragma unroll
-    for (int fn = 0; fn < Lt::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + acc_row(T(0), lane, i);
-        const int gc = n0 + wn * Lt::TN + fn * 16 + (lane & 15);
-        if (gr < J.M && gc < a.nrhs) dst[map_row(a.rowmap, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
+    for (int i = 0; i < 4; ++i) {
+      const int gr = tile.m0 + wave * 16 + acc_row(T(0), lane, i);
+      const int gc = n0 + fn * 16 + lrow;
+      if (gr < J.M && gc < a.nrhs) {
+        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
+        dst[drow * a.ldd + gc] = acc[fn][i];
       }
+    }
 }
 
 // Transposed stage: dst[out_row .. out_row+K) = sum over consumers of W_c^T g_c,
 // identity consumers adding their gradient rows directly.
 template <typename T, int BN>
 __global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
-  typedef Layout<BN> Lt;
-  __shared__ T As[kBM][kBK + 1];
-  __shared__ T Bs[kBK][BN + 1];
+  typedef Tiling<T, BN> Tl;
+  __shared__ __attribute__((aligned(16))) T Xs[2 * Tl::XBUF];
   const Tile tile = a.tiles[blockIdx.x];
+  if (tile.job < 0) return;  // padding tile of a short XCD bin
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
   const int n0 = blockIdx.y * BN;
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / Lt::WN, wn = wave % Lt::WN;
-  typename Acc4<T>::type acc[Lt::FM][Lt::FN];
+  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int row = min(tile.m0 + wave * 16 + lrow, J.K - 1);  // row of W^T (column of W)
+  typename Cfg<T>::acc_t acc[Tl::FN];
 #pragma unroll
-  for (int i = 0; i < Lt::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < Lt::FN; ++j) acc[i][j] = typename Acc4<T>::type{0, 0, 0, 0};
+  for (int i = 0; i < Tl::FN; ++i) acc[i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
 
   for (int ci = 0; ci < J.nc; ++ci) {
     const Cons C = J.c[ci];
-    if (C.w_off < 0) continue;
-    const T *W = static_cast<const T *>(a.pool) + C.w_off;
-    for (int k0 = 0; k0 < C.M; k0 += kBK) {
-      // A[r][k] = W[k0 + k][m0 + r]  (W^T restricted to this tile)
-      for (int e = tid; e < kBM * kBK; e += kNT) {
-        const int k = e / kBM, r = e % kBM;
-        const int gr = tile.m0 + r, gk = k0 + k;
-        As[r][k] = (gr < J.K && gk < C.M) ? W[(int64_t)gk * C.ldw + gr] : T(0);
-      }
-      for (int e = tid; e < kBK * BN; e += kNT) {
-        const int k = e / BN, c = e % BN;
-        const int gk = k0 + k, gc = n0 + c;
-        Bs[k][c] = (gk < C.M && gc < a.nrhs) ? src[map_row(a.rowmap, C.g_row, gk) * a.lds + gc] : T(0);
-      }
-      __syncthreads();
-      mma_round<T, BN>(As, Bs, acc, wm, wn, lane);
-      __syncthreads();
-    }
+    if (C.wt_off < 0) continue;
+    const T *wrow = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)row * C.ldwt;
+    gemm_block<T, BN>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
   }
 
 #pragma unroll
-  for (int fm = 0; fm < Lt::FM; ++fm)
+  for (int fn = 0; fn < Tl::FN; ++fn)
 #pragma unroll
-    for (int fn = 0; fn < Lt::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = tile.m0 + wm * Lt::TM + fm * 16 + acc_row(T(0), lane, i);
-        const int gc = n0 + wn * Lt::TN + fn * 16 + (lane & 15);
-        if (gr < J.K && gc < a.nrhs) {
-          T v = acc[fm][fn][i];
-          for (int ci = 0; ci < J.nc; ++ci)
-            if (J.c[ci].w_off < 0) v += src[map_row(a.rowmap, J.c[ci].g_row, gr) * a.lds + gc];
-          dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
-        }
+    for (int i = 0; i < 4; ++i) {
+      const int gr = tile.m0 + wave * 16 + acc_row(T(0), lane, i);
+      const int gc = n0 + fn * 16 + lrow;
+      if (gr < J.K && gc < a.nrhs) {
+        T v = acc[fn][i];
+        for (int ci = 0; ci < J.nc; ++ci)
+          if (J.c[ci].wt_off < 0) {
+            const int32_t b = J.c[ci].g_row;
+            const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
+            v += src[srow * a.lds + gc];
+          }
+        dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
       }
+    }
 }
 
 template <typename T, int BN>

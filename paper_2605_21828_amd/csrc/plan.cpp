@@ -9,6 +9,7 @@
 // ld = nrhs, blocks in space-major order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -66,9 +67,10 @@ struct bfmht_plan {
   std::vector<StageDesc> stages;
   std::vector<int64_t> level_rows;
   int64_t max_rows = 0;
-  int64_t pool_elems = 0;
+  int64_t pool_elems = 0, tpool_elems = 0;
   int64_t stored_entries = 0;  // factor entries that are read once per apply (no padding)
-  int64_t off_pool[3] = {0, 0, 0};
+  int64_t off_pool[3] = {0, 0, 0};   // forward pool, one region per term
+  int64_t off_tpool[3] = {0, 0, 0};  // transposed pool
   int64_t off_fjobs = 0, off_bjobs = 0, off_tiles = 0, off_perm = 0, dev_bytes = 0;
   std::vector<unsigned char> staging;
   char *dev = nullptr;
@@ -171,11 +173,14 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     p->max_rows = std::max(p->max_rows, off[lvl][nb]);
   }
 
-  // Pool offsets of every stored block.
+  // Pool offsets of every stored block: W (rows x cols, stride ldw_of(cols)) in
+  // the forward pool and W^T (cols x rows, stride ldw_of(rows)) in the
+  // transposed pool, in the same block order.
   struct Src { const double *ptr; int64_t rows, cols; };
   std::vector<Src> blocks;
   std::vector<int64_t> woff_P((size_t)(L + 1) * nb, -1), woff_U(nb, -1);
-  int64_t pool = 0;
+  std::vector<int64_t> wtoff_P((size_t)(L + 1) * nb, -1), wtoff_U(nb, -1);
+  int64_t pool = 0, tpool = 0;
   auto rin_of = [&](int lvl, int64_t q) -> int64_t {
     if (lvl == 0) return f->koff[q + 1] - f->koff[q];
     const int64_t nf = 1ll << (L - lvl), i = q / nf, j = q % nf, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
@@ -186,42 +191,85 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
       if (f->ident[lvl * nb + q]) continue;
       const int64_t r = f->rank[lvl * nb + q], k = rin_of(lvl, q);
       woff_P[lvl * nb + q] = pool;
+      wtoff_P[lvl * nb + q] = tpool;
       blocks.push_back({r * k ? f->P + f->P_off[lvl * nb + q] : nullptr, r, k});
       pool += r * ldw_of(k);
+      tpool += k * ldw_of(r);
       p->stored_entries += r * k;
     }
   for (int64_t i = 0; i < nb; ++i) {
     const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
     woff_U[i] = pool;
+    wtoff_U[i] = tpool;
     blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r});
     pool += rows * ldw_of(r);
+    tpool += r * ldw_of(rows);
     p->stored_entries += rows * r;
   }
   p->pool_elems = pool;
+  p->tpool_elems = tpool;
 
   // Stage tables.
   std::vector<FwdJob> fj;
   std::vector<BwdJob> bj;
   std::vector<Tile> tiles;
-  const int BM = tile_rows(prec, max_nrhs);
+  const int BM = kTileRows;
+  // Workgroups of one launch go to the 8 XCDs round robin (workgroup b to XCD
+  // b % 8), each XCD with its own L2.  Jobs are packed into 8 bins by cost
+  // (longest first), each bin's tiles keep their job's tiles together so the
+  // job's right-hand-side rows are fetched into one L2, and the bins are
+  // interleaved so bin x lands on XCD x; short bins are padded with empty tiles.
+  auto order = [&](std::vector<std::pair<int64_t, int64_t>> jobs_cost_rows, int64_t job0) {
+    const int X = 8;
+    std::vector<int64_t> idx(jobs_cost_rows.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      return jobs_cost_rows[a].first * ((jobs_cost_rows[a].second + BM - 1) / BM) >
+             jobs_cost_rows[b].first * ((jobs_cost_rows[b].second + BM - 1) / BM);
+    });
+    std::vector<std::vector<Tile>> bins(X);
+    std::vector<int64_t> load(X, 0);
+    for (int64_t j : idx) {
+      const int64_t rows = jobs_cost_rows[j].second;
+      if (rows <= 0) continue;
+      int x = 0;
+      for (int y = 1; y < X; ++y)
+        if (load[y] < load[x]) x = y;
+      for (int32_t m0 = 0; m0 < rows; m0 += BM) {
+        bins[x].push_back({(int32_t)j, m0});
+        load[x] += std::max<int64_t>(jobs_cost_rows[j].first, 1);
+      }
+    }
+    size_t len = 0;
+    for (auto &b : bins) len = std::max(len, b.size());
+    const size_t start = tiles.size();
+    for (size_t s = 0; s < len; ++s)
+      for (int x = 0; x < X; ++x) tiles.push_back(s < bins[x].size() ? bins[x][s] : Tile{-1, 0});
+    (void)job0;
+    return (int64_t)(tiles.size() - start);
+  };
   auto add_ftiles = [&](StageDesc &s) {
     s.ftile0 = (int64_t)tiles.size();
-    for (int64_t t = s.fjob0; t < s.fjob0 + s.nfjob; ++t)
-      for (int32_t m0 = 0; m0 < fj[t].M; m0 += BM) tiles.push_back({(int32_t)(t - s.fjob0), m0});
-    s.nftile = (int64_t)tiles.size() - s.ftile0;
+    std::vector<std::pair<int64_t, int64_t>> jc;
+    for (int64_t t = s.fjob0; t < s.fjob0 + s.nfjob; ++t) jc.push_back({fj[t].w_off < 0 ? 1 : fj[t].K, fj[t].M});
+    s.nftile = order(jc, s.fjob0);
   };
   auto add_btiles = [&](StageDesc &s) {
     s.btile0 = (int64_t)tiles.size();
-    for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t)
-      for (int32_t m0 = 0; m0 < bj[t].K; m0 += BM) tiles.push_back({(int32_t)(t - s.bjob0), m0});
-    s.nbtile = (int64_t)tiles.size() - s.btile0;
+    std::vector<std::pair<int64_t, int64_t>> jc;
+    for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t) {
+      int64_t cost = 1;
+      for (int c = 0; c < bj[t].nc; ++c) cost += bj[t].c[c].M;
+      jc.push_back({cost, bj[t].K});
+    }
+    s.nbtile = order(jc, s.bjob0);
   };
   auto cons_of = [&](int lvl, int64_t q) -> Cons {
     Cons c;
     const bool id = f->ident[lvl * nb + q] != 0;
-    c.w_off = id ? -1 : woff_P[lvl * nb + q];
+    c.wt_off = id ? -1 : wtoff_P[lvl * nb + q];
     c.M = f->rank[lvl * nb + q];
-    c.ldw = ldw_of(rin_of(lvl, q));
+    c.ldwt = ldw_of(c.M);
     c.g_row = (int32_t)off[lvl][q];
     c.pad = 0;
     return c;
@@ -273,9 +321,9 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
         b.K = (int32_t)r;
         b.out_row = (int32_t)off[L][i];
         b.nc = 1;
-        b.c[0].w_off = woff_U[i];
+        b.c[0].wt_off = woff_U[i] >= 0 ? wtoff_U[i] : -1;
         b.c[0].M = (int32_t)rows;
-        b.c[0].ldw = ldw_of(r);
+        b.c[0].ldwt = ldw_of(rows);
         b.c[0].g_row = (int32_t)f->xoff[i];
         bj.push_back(b);
       }
@@ -295,6 +343,10 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     p->off_pool[t] = cur;
     cur = align_up(cur + pool * p->wsz, 256);
   }
+  for (int t = 0; t < p->nterms; ++t) {
+    p->off_tpool[t] = cur;
+    cur = align_up(cur + tpool * p->wsz, 256);
+  }
   p->off_fjobs = cur;
   cur = align_up(cur + (int64_t)fj.size() * (int64_t)sizeof(FwdJob), 256);
   p->off_bjobs = cur;
@@ -312,29 +364,32 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     return fail(BFMHT_ENOSPACE, "host staging allocation failed");
   }
   unsigned char *S = p->staging.data();
-  int64_t bo = 0;
+  auto put = [&](const int64_t *base, int64_t e, double x) {
+    if (prec == BFMHT_F64) {
+      reinterpret_cast<double *>(S + base[0])[e] = x;
+    } else if (prec == BFMHT_F32) {
+      reinterpret_cast<float *>(S + base[0])[e] = (float)x;
+    } else {
+      const float x32 = (float)x;
+      const uint16_t hi = f32_to_bf16(x32);
+      const float r1 = x32 - bf16_to_f32(hi);
+      const uint16_t lo = f32_to_bf16(r1);
+      reinterpret_cast<uint16_t *>(S + base[0])[e] = hi;
+      reinterpret_cast<uint16_t *>(S + base[1])[e] = lo;
+      if (p->nterms == 3) reinterpret_cast<uint16_t *>(S + base[2])[e] = f32_to_bf16(r1 - bf16_to_f32(lo));
+    }
+  };
+  int64_t bo = 0, tbo = 0;
   for (const Src &b : blocks) {
-    const int64_t ld = ldw_of(b.cols);
+    const int64_t ld = ldw_of(b.cols), ldt = ldw_of(b.rows);
     for (int64_t r = 0; r < b.rows; ++r)
       for (int64_t c = 0; c < b.cols; ++c) {
         const double x = b.ptr[r * b.cols + c];
-        const int64_t e = bo + r * ld + c;
-        if (prec == BFMHT_F64) {
-          reinterpret_cast<double *>(S + p->off_pool[0])[e] = x;
-        } else if (prec == BFMHT_F32) {
-          reinterpret_cast<float *>(S + p->off_pool[0])[e] = (float)x;
-        } else {
-          const float x32 = (float)x;
-          const uint16_t hi = f32_to_bf16(x32);
-          const float r1 = x32 - bf16_to_f32(hi);
-          const uint16_t lo = f32_to_bf16(r1);
-          reinterpret_cast<uint16_t *>(S + p->off_pool[0])[e] = hi;
-          reinterpret_cast<uint16_t *>(S + p->off_pool[1])[e] = lo;
-          if (p->nterms == 3)
-            reinterpret_cast<uint16_t *>(S + p->off_pool[2])[e] = f32_to_bf16(r1 - bf16_to_f32(lo));
-        }
+        put(p->off_pool, bo + r * ld + c, x);
+        put(p->off_tpool, tbo + c * ldt + r, x);
       }
     bo += b.rows * ld;
+    tbo += b.cols * ldt;
   }
   if (!fj.empty()) std::memcpy(S + p->off_fjobs, fj.data(), fj.size() * sizeof(FwdJob));
   if (!bj.empty()) std::memcpy(S + p->off_bjobs, bj.data(), bj.size() * sizeof(BwdJob));
@@ -387,11 +442,17 @@ bfmht_status check_call(const bfmht_plan *p, const void *in, int64_t ldin, const
   return BFMHT_OK;
 }
 
+// Source rows may be read with 16-byte loads when the base and row pitch are 16-byte aligned.
+int32_t vec_ok(const void *src, int64_t ld, int64_t esz) {
+  return (((uintptr_t)src) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
+}
+
 StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
   StageArgs a{};
-  a.pool = p->dev + p->off_pool[0];
-  a.pool_lo = p->nterms > 1 ? p->dev + p->off_pool[1] : nullptr;
-  a.pool_lo2 = p->nterms > 2 ? p->dev + p->off_pool[2] : nullptr;
+  const int64_t *po = fwd ? p->off_pool : p->off_tpool;
+  a.pool = p->dev + po[0];
+  a.pool_lo = p->nterms > 1 ? p->dev + po[1] : nullptr;
+  a.pool_lo2 = p->nterms > 2 ? p->dev + po[2] : nullptr;
   if (fwd) {
     a.jobs = p->dev + p->off_fjobs + s.fjob0 * (int64_t)sizeof(FwdJob);
     a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.ftile0;
@@ -431,6 +492,7 @@ bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *
       a.dst = buf[s.level & 1];
       a.ldd = nrhs;
     }
+    a.vec = vec_ok(a.src, a.lds, p->esz);
     const int e = launch_fwd_stage(p->prec, a, stream);
     if (e) return fail(BFMHT_EHIP, std::string("apply stage launch: ") + hipGetErrorString((hipError_t)e));
   }
@@ -461,6 +523,7 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t l
       a.dst = buf[(s.level - 1) & 1];
       a.ldd = nrhs;
     }
+    a.vec = vec_ok(a.src, a.lds, p->esz);
     const int e = launch_bwd_stage(p->prec, a, stream);
     if (e) return fail(BFMHT_EHIP, std::string("apply_transpose stage launch: ") + hipGetErrorString((hipError_t)e));
   }
