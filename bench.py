@@ -82,7 +82,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="iid65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--variants", default="f64,bf16x2,bf16x3",
+                    help="comma list of other precisions timed on the same inputs")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
     args = ap.parse_args()
@@ -145,28 +146,40 @@ def main():
         "stored_factor_entries": F, "compression_vs_dense": n * m / F,
         "stage_launches_per_apply": launches,
     }
+    variants_out = {}
 
-    if not args.no_f64:
-        log("uploading FP64 plan")
-        p64 = Plan(fs, "f64", max_nrhs=b, device=dev)
-        c64 = torch.tensor(c_host, dtype=torch.float64, device=dev)
-        f64 = torch.tensor(f_host, dtype=torch.float64, device=dev)
-        y64 = torch.empty((n, b), dtype=torch.float64, device=dev)
-        g64 = torch.empty((m, b), dtype=torch.float64, device=dev)
+    # Precision variants on the same inputs: the plain FP64 apply (speedup
+    # reference and accuracy anchor) and the BF16 split products.
+    variants = [v for v in args.variants.split(",") if v]
+    y64 = None
+    for prec in variants:
+        log("uploading %s plan" % prec)
+        pv = Plan(fs, prec, max_nrhs=b, device=dev)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        cv = c32.to(dt) if prec != "f64" else torch.tensor(c_host, dtype=dt, device=dev)
+        fv = f32.to(dt) if prec != "f64" else torch.tensor(f_host, dtype=dt, device=dev)
+        yv = torch.empty((n, b), dtype=dt, device=dev)
+        gv = torch.empty((m, b), dtype=dt, device=dev)
         for _ in range(2):
-            p64.apply(c64, out=y64)
-            p64.apply_t(f64, out=g64)
-        ms64_fwd = event_time(lambda: p64.apply(c64, out=y64), reps, torch)
-        ms64_bwd = event_time(lambda: p64.apply_t(f64, out=g64), reps, torch)
-        d32 = y32.double()
-        rel = float(torch.linalg.norm(d32 - y64) / torch.linalg.norm(y64))
-        result_extra.update({
-            "fp64_plain_apply_ms": ms64_fwd, "fp64_plain_apply_transpose_ms": ms64_bwd,
-            "speedup_fp32_vs_fp64_plain": (ms64_fwd + ms64_bwd) / (ms_fwd + ms_bwd),
-            "fp32_vs_fp64_gpu_rel_err": rel,
-        })
-        del p64, c64, f64, y64, g64, d32
+            pv.apply(cv, out=yv)
+            pv.apply_t(fv, out=gv)
+        t_f = event_time(lambda: pv.apply(cv, out=yv), reps, torch)
+        t_b = event_time(lambda: pv.apply_t(fv, out=gv), reps, torch)
+        rec = {"apply_ms": t_f, "apply_transpose_ms": t_b,
+               "speedup_vs_fp32": (ms_fwd + ms_bwd) / (t_f + t_b),
+               "plan_device_GB": pv.device_bytes / 1e9}
+        if prec == "f64":
+            y64 = yv.clone()
+        elif y64 is not None:
+            rec["rel_err_vs_fp64_gpu"] = float(torch.linalg.norm(yv.double() - y64) / torch.linalg.norm(y64))
+        variants_out[prec] = rec
+        del pv, cv, fv, yv, gv
         torch.cuda.empty_cache()
+    if y64 is not None:
+        result_extra["fp32_vs_fp64_gpu_rel_err"] = float(torch.linalg.norm(y32.double() - y64) / torch.linalg.norm(y64))
+        result_extra["speedup_fp32_vs_fp64_plain"] = ((variants_out["f64"]["apply_ms"] + variants_out["f64"]["apply_transpose_ms"])
+                                                      / (ms_fwd + ms_bwd))
+    result_extra["variants"] = variants_out
 
     base = None
     if not args.no_cpu_baseline:

@@ -259,6 +259,261 @@ __global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 split products.  A factor value w is stored as 2 or 3 bfloat16 terms
+// (hi = bf16(w), lo = bf16(w - hi), lo2 = bf16(w - hi - lo)); right-hand-side
+// values are split the same way when a chunk is staged into LDS (once per
+// workgroup).  Products of terms whose indices sum to at most NT-1 are
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16: hi*hi + hi*lo + lo*hi for
+// two terms, plus hi*lo2 + lo*lo + lo2*hi for three.  Only the output layout of
+// the instruction matters here: both operands use the same (lane group, element)
+// -> k assignment, so any internal ordering of k is summed the same way.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);  // finite inputs: round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ v4f mfma_bf16(const uint4 &a, const uint4 &b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                 0);
+}
+
+template <int NTERM, int BN>
+struct TilingB {
+  static constexpr int KC = 64;               // reduction depth per chunk
+  static constexpr int KL = KC / 4;           // values per lane per chunk (two 8-value MFMA steps)
+  static constexpr int FN = BN / 16;
+  static constexpr int XS = KC + 8;           // LDS row stride in bf16 (16-byte padding)
+  static constexpr int XBUF = BN * XS;        // bf16 per term per buffer
+  static constexpr int XR = KC * BN / kNT;    // RHS values staged per thread per chunk
+  static_assert(XR >= 1 && BN % XR == 0, "staging split");
+};
+
+// Stage one FP32 RHS chunk (rows k0..k0+KC) split into NTERM bf16 terms, transposed.
+template <int NTERM, int BN>
+__device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
+                                          int32_t nrows, int k0, int n0, int tid) {
+  typedef TilingB<NTERM, BN> Tl;
+  const int e = tid * Tl::XR;
+  const int k = e / BN, c = e % BN;
+  const int gk = k0 + k;
+#pragma unroll
+  for (int i = 0; i < Tl::XR; ++i) xr[i] = 0.f;
+  if (gk >= nrows) return;
+  const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
+  const float *p = static_cast<const float *>(a.src) + srow * a.lds + n0 + c;
+  if (a.vec && n0 + c + Tl::XR <= a.nrhs) {
+    copy_vec<float, Tl::XR>(xr, p);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Tl::XR; ++i)
+      if (n0 + c + i < a.nrhs) xr[i] = p[i];
+  }
+}
+
+template <int NTERM, int BN>
+__device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int tid) {
+  typedef TilingB<NTERM, BN> Tl;
+  const int e = tid * Tl::XR;
+  const int k = e / BN, c = e % BN;
+#pragma unroll
+  for (int i = 0; i < Tl::XR; ++i) {
+    const float x = xr[i];
+    const uint16_t h = f32_to_bf16_rne(x);
+    const float r = x - bf16_to_f32(h);
+    const uint16_t l = f32_to_bf16_rne(r);
+    Xs[(c + i) * Tl::XS + k] = h;
+    Xs[Tl::XBUF * 2 + (c + i) * Tl::XS + k] = l;
+    if constexpr (NTERM == 3) Xs[Tl::XBUF * 4 + (c + i) * Tl::XS + k] = f32_to_bf16_rne(r - bf16_to_f32(l));
+  }
+}
+
+// This lane's KL factor values of each term for the chunk at k0 (32 bytes per
+// term).  Row strides are multiples of 8 values, so each 8-value half is either
+// entirely inside the row or entirely past its end.
+template <int NTERM, int BN>
+__device__ __forceinline__ void load_w_bf(uint4 (&wr)[NTERM][2], const uint16_t *const (&wrow)[3], int ldw, int k0,
+                                          int lg) {
+  typedef TilingB<NTERM, BN> Tl;
+  const int k = k0 + Tl::KL * lg;
+#pragma unroll
+  for (int t = 0; t < NTERM; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      wr[t][h] = k + 8 * h < ldw ? *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h) : make_uint4(0, 0, 0, 0);
+}
+
+template <int NTERM, int BN>
+__device__ __forceinline__ void mma_chunk_bf(v4f *acc, const uint4 (&wr)[NTERM][2], const uint16_t *Xs, int lrow,
+                                             int lg) {
+  typedef TilingB<NTERM, BN> Tl;
+#pragma unroll
+  for (int fn = 0; fn < Tl::FN; ++fn) {
+    const int off = (fn * 16 + lrow) * Tl::XS + Tl::KL * lg;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 b[NTERM];
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) b[t] = *reinterpret_cast<const uint4 *>(Xs + t * 2 * Tl::XBUF + off + 8 * h);
+      // smallest products first
+      if constexpr (NTERM == 3) {
+        acc[fn] = mfma_bf16(wr[2][h], b[0], acc[fn]);
+        acc[fn] = mfma_bf16(wr[1][h], b[1], acc[fn]);
+        acc[fn] = mfma_bf16(wr[0][h], b[2], acc[fn]);
+      }
+      acc[fn] = mfma_bf16(wr[1][h], b[0], acc[fn]);
+      acc[fn] = mfma_bf16(wr[0][h], b[1], acc[fn]);
+      acc[fn] = mfma_bf16(wr[0][h], b[0], acc[fn]);
+    }
+  }
+}
+
+// Reduction over one factor block with split terms.  Xs holds 2 buffers per
+// term: term t buffer j at Xs + (2 t + j) * XBUF.
+template <int NTERM, int BN>
+__device__ __forceinline__ void gemm_block_bf(v4f *acc, const uint16_t *const (&wrow)[3], int ldw, int nk,
+                                              const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
+                                              uint16_t *Xs, int tid, int lrow, int lg) {
+  typedef TilingB<NTERM, BN> Tl;
+  const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
+  if (nchunk == 0) return;
+  uint4 wA[NTERM][2], wB[NTERM][2];
+  float xB[Tl::XR];
+  load_w_bf<NTERM, BN>(wA, wrow, ldw, 0, lg);
+  load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
+  store_x_bf<NTERM, BN>(Xs, xB, tid);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const bool more = c + 1 < nchunk;
+    if (more) {
+      load_w_bf<NTERM, BN>(wB, wrow, ldw, (c + 1) * Tl::KC, lg);
+      load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
+    }
+    mma_chunk_bf<NTERM, BN>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    if (more) {
+      store_x_bf<NTERM, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) {
+        wA[t][0] = wB[t][0];
+        wA[t][1] = wB[t][1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NTERM, int BN>
+__global__ __launch_bounds__(kNT) void fwd_stage_bf16_kernel(StageArgs a) {
+  typedef TilingB<NTERM, BN> Tl;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * Tl::XBUF];
+  const Tile tile = a.tiles[blockIdx.x];
+  if (tile.job < 0) return;  // padding tile of a short XCD bin
+  const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
+  const int n0 = blockIdx.y * BN;
+  const float *src = static_cast<const float *>(a.src);
+  float *dst = static_cast<float *>(a.dst);
+  const int tid = threadIdx.x;
+
+  if (J.w_off < 0) {  // identity block: copy its rows
+    for (int e = tid; e < kTileRows * BN; e += kNT) {
+      const int r = e / BN, c = e % BN;
+      const int gr = tile.m0 + r, gc = n0 + c;
+      if (gr < J.M && gc < a.nrhs) {
+        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
+        dst[drow * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
+      }
+    }
+    return;
+  }
+  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int row = tile.m0 + wave * 16 + lrow;
+  const int64_t roff = J.w_off + (int64_t)min(row, J.M - 1) * J.ldw;
+  const uint16_t *const wrow[3] = {static_cast<const uint16_t *>(a.pool) + roff,
+                                   static_cast<const uint16_t *>(a.pool_lo) + roff,
+                                   NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr};
+  v4f acc[Tl::FN];
+#pragma unroll
+  for (int i = 0; i < Tl::FN; ++i) acc[i] = v4f{0, 0, 0, 0};
+  gemm_block_bf<NTERM, BN>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+#pragma unroll
+  for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gr = tile.m0 + wave * 16 + acc_row(0.f, lane, i);
+      const int gc = n0 + fn * 16 + lrow;
+      if (gr < J.M && gc < a.nrhs) {
+        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
+        dst[drow * a.ldd + gc] = acc[fn][i];
+      }
+    }
+}
+
+template <int NTERM, int BN>
+__global__ __launch_bounds__(kNT) void bwd_stage_bf16_kernel(StageArgs a) {
+  typedef TilingB<NTERM, BN> Tl;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * Tl::XBUF];
+  const Tile tile = a.tiles[blockIdx.x];
+  if (tile.job < 0) return;  // padding tile of a short XCD bin
+  const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
+  const int n0 = blockIdx.y * BN;
+  const float *src = static_cast<const float *>(a.src);
+  float *dst = static_cast<float *>(a.dst);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int row = min(tile.m0 + wave * 16 + lrow, J.K - 1);
+  v4f acc[Tl::FN];
+#pragma unroll
+  for (int i = 0; i < Tl::FN; ++i) acc[i] = v4f{0, 0, 0, 0};
+  for (int ci = 0; ci < J.nc; ++ci) {
+    const Cons C = J.c[ci];
+    if (C.wt_off < 0) continue;
+    const int64_t roff = C.wt_off + (int64_t)row * C.ldwt;
+    const uint16_t *const wrow[3] = {static_cast<const uint16_t *>(a.pool) + roff,
+                                     static_cast<const uint16_t *>(a.pool_lo) + roff,
+                                     NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr};
+    gemm_block_bf<NTERM, BN>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
+  }
+#pragma unroll
+  for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gr = tile.m0 + wave * 16 + acc_row(0.f, lane, i);
+      const int gc = n0 + fn * 16 + lrow;
+      if (gr < J.K && gc < a.nrhs) {
+        float v = acc[fn][i];
+        for (int ci = 0; ci < J.nc; ++ci)
+          if (J.c[ci].wt_off < 0) {
+            const int32_t b = J.c[ci].g_row;
+            const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
+            v += src[srow * a.lds + gc];
+          }
+        dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+      }
+    }
+}
+
+template <int NTERM, int BN>
+static int launch_bf_t(bool fwd, const StageArgs &a, void *stream) {
+  if (a.ntiles == 0) return 0;
+  dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
+  if (fwd)
+    hipLaunchKernelGGL((fwd_stage_bf16_kernel<NTERM, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL((bwd_stage_bf16_kernel<NTERM, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+template <int NTERM>
+static int launch_bf(bool fwd, const StageArgs &a, void *stream) {
+  if (a.nrhs <= 16) return launch_bf_t<NTERM, 16>(fwd, a, stream);
+  if (a.nrhs <= 32) return launch_bf_t<NTERM, 32>(fwd, a, stream);
+  return launch_bf_t<NTERM, 64>(fwd, a, stream);
+}
+
 template <typename T, int BN>
 static int launch_t(bool fwd, const StageArgs &a, void *stream) {
   if (a.ntiles == 0) return 0;
@@ -281,6 +536,8 @@ static int launch(bool fwd, int prec, const StageArgs &a, void *stream) {
   switch (prec) {
     case P_F64: return launch_bn<double>(fwd, a, stream);
     case P_F32: return launch_bn<float>(fwd, a, stream);
+    case P_BF16X2: return launch_bf<2>(fwd, a, stream);
+    case P_BF16X3: return launch_bf<3>(fwd, a, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }

@@ -186,3 +186,67 @@ def test_workspace_too_small_is_rejected(gpu):
     with pytest.raises(B.BfmhtError) as e:
         B.bfmht_plan_upload(p.handle, p._dev_ptr, p.device_bytes, 0)
     assert e.value.status == B.ESTATE
+
+
+# ---- BF16 split products ----
+# A value split into t bfloat16 terms (8 significand bits each, round to
+# nearest) is represented to 2^-8t relative.  BF16X2 keeps hi*hi + hi*lo +
+# lo*hi, so one product differs from the exact one by at most about 3 * 2^-16
+# of |w||x|; BF16X3 keeps the six products with term-index sum <= 2 and is good
+# to a few 2^-24.  Over the L+2 stages of an apply the error of every output is
+# then bounded by (L+2) * gamma * (|Phi~| |c|), where |Phi~| multiplies the
+# absolute values of the factors; gamma below adds headroom for FP32
+# accumulation (2^-14 for X2, 2^-21 for X3).  Relative bars are also asserted on
+# realistic (non-cancelling) inputs: 1e-5 for X3, 1e-4 for X2.
+BF16_GAMMA = {"bf16x2": 2.0 ** -14, "bf16x3": 2.0 ** -21}
+BF16_TOL = {"bf16x3": 1e-5, "bf16x2": 1e-4}
+
+
+def _abs_factors(fs):
+    return dict(fs, P=np.abs(fs["P"]), U=np.abs(fs["U"]))
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "bf16x3"])
+@pytest.mark.parametrize("case", RANDOM_CASES)
+@pytest.mark.parametrize("nrhs", [1, 40, 64])
+def test_random_factors_bf16_within_error_bound(gpu, prec, case, nrhs):
+    import torch
+    seed, n, m, L, mr = case
+    fs = random_factor_set(seed, n, m, L, max_rank=mr)
+    fa = _abs_factors(fs)
+    rng = np.random.default_rng(seed + 300)
+    c, f = rng.standard_normal((m, nrhs)), rng.standard_normal((n, nrhs))
+    p = _plan(fs, prec, nrhs)
+    k = (L + 2) * BF16_GAMMA[prec]
+    y = _np(p.apply(_t(c, torch.float32)))
+    assert np.all(np.abs(y - ob.apply(fs, c)) <= k * ob.apply(fa, np.abs(c)) + 1e-30)
+    g = _np(p.apply_t(_t(f, torch.float32)))
+    assert np.all(np.abs(g - ob.apply_transpose(fs, f)) <= k * ob.apply_transpose(fa, np.abs(f)) + 1e-30)
+    if prec == "bf16x3" and n >= 64:
+        assert _rel(y, ob.apply(fs, c)) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "bf16x3"])
+def test_bf16_permutation_is_bit_exact(gpu, prec):
+    import torch
+    n = 1000
+    fs = random_factor_set(37, n, n, 4, identity_values=True)
+    c = np.arange(n * 5, dtype=np.float64).reshape(n, 5)   # integers < 2^16: exact in two bf16 terms
+    p = _plan(fs, prec, 5)
+    f = _np(p.apply(_t(c, torch.float32)))
+    assert np.array_equal(f[fs["perm_x"]], c)
+    assert np.array_equal(_np(p.apply_t(_t(f, torch.float32))), c)
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "bf16x3"])
+def test_iid_bf16_vs_dense(gpu, iid_medium, prec):
+    import torch
+    wid, pts, fs, md = iid_medium
+    Phi = om.phi(pts, md)
+    c = wl.coefficients(wid, 2048, 64, lam=om.eigenvalues(md), kind="decay")
+    fv = wl.values(wid, 8192, 64)
+    p = _plan(fs, prec, 64)
+    e1 = _rel(_np(p.apply(_t(c, torch.float32))), Phi @ c)
+    e2 = _rel(_np(p.apply_t(_t(fv, torch.float32))), Phi.T @ fv)
+    print("%s synthesis %.2e analysis %.2e" % (prec, e1, e2))
+    assert e1 <= BF16_TOL[prec] and e2 <= BF16_TOL[prec]
