@@ -132,6 +132,37 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_
                                    int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
                                    void *stream);
 
+/* Number of stages of one apply: L + 2 (level 0, the L transfer levels, the
+ * leaf stage), numbered in forward order; -1 for NULL. */
+int32_t bfmht_plan_num_stages(const bfmht_plan *plan);
+
+/* Tile width (right-hand-side columns per workgroup tile) of one stage of the
+ * forward (transpose = 0) or transposed (transpose != 0) apply: 16, 32 or 64,
+ * or 0 for the default (the smallest of 16, 32, 64 that covers nrhs).  Results
+ * do not depend on it; it is the knob the autotuner sets.  EINVAL on a bad
+ * stage or width. */
+bfmht_status bfmht_plan_set_tile_cols(bfmht_plan *plan, int32_t transpose, int32_t stage, int32_t cols);
+/* The value set for that stage (0 = default), -1 on a bad argument. */
+int32_t bfmht_plan_get_tile_cols(const bfmht_plan *plan, int32_t transpose, int32_t stage);
+
+/* Workspace bytes of a bfmht_apply_batched call with these plans and RHS
+ * counts (count >= 0 plans, all of one precision); -1 on a bad argument. */
+int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs);
+
+/* Many instances of uneven size, grouped per launch.  Instance i applies
+ * plans[i] (forward when transpose == 0, else transposed) to in[i] (rows x
+ * nrhs[i], ld ldin[i]) and overwrites out[i] (ld ldout[i]); instances with
+ * nrhs[i] == 0 are skipped.  All plans must be uploaded and share one
+ * precision.  Launch k runs the k-th stage of every instance at once (one work
+ * item per output tile of each instance), so the number of launches is the
+ * largest stage count in the batch, not the sum over instances.  ws: device
+ * workspace, 256-byte aligned, at least bfmht_batched_workspace_bytes; it
+ * holds the per-call tables (copied from host memory on `stream`) and each
+ * instance's level buffers, so calls that overlap on one workspace race. */
+bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
+                                 const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream);
+
 /* Free the plan's host memory.  Does not touch device memory.  NULL is a no-op. */
 void bfmht_plan_destroy(bfmht_plan *plan);
 

@@ -39,6 +39,8 @@ class bfmht_factors_host(ctypes.Structure):
 EXPORTED = [
     "bfmht_plan_create", "bfmht_plan_device_bytes", "bfmht_workspace_bytes", "bfmht_plan_upload",
     "bfmht_apply", "bfmht_apply_transpose", "bfmht_plan_destroy", "bfmht_last_error", "bfmht_version",
+    "bfmht_plan_num_stages", "bfmht_plan_set_tile_cols", "bfmht_plan_get_tile_cols",
+    "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
 ]
 
 
@@ -65,6 +67,18 @@ def load_library(path=LIB_PATH):
     lib.bfmht_last_error.restype = ctypes.c_char_p
     lib.bfmht_version.argtypes = []
     lib.bfmht_version.restype = ctypes.c_char_p
+    lib.bfmht_plan_num_stages.argtypes = [vp]
+    lib.bfmht_plan_num_stages.restype = i32
+    lib.bfmht_plan_set_tile_cols.argtypes = [vp, i32, i32, i32]
+    lib.bfmht_plan_set_tile_cols.restype = ctypes.c_int
+    lib.bfmht_plan_get_tile_cols.argtypes = [vp, i32, i32]
+    lib.bfmht_plan_get_tile_cols.restype = i32
+    pp = ctypes.POINTER(vp)
+    lib.bfmht_batched_workspace_bytes.argtypes = [pp, i32, ctypes.POINTER(i32)]
+    lib.bfmht_batched_workspace_bytes.restype = i64
+    lib.bfmht_apply_batched.argtypes = [pp, i32, pp, ctypes.POINTER(i64), pp, ctypes.POINTER(i64),
+                                        ctypes.POINTER(i32), i32, vp, i64, vp]
+    lib.bfmht_apply_batched.restype = ctypes.c_int
     return lib
 
 
@@ -136,6 +150,33 @@ def bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, 
 
 def bfmht_plan_destroy(plan):
     lib.bfmht_plan_destroy(plan)
+
+
+def bfmht_plan_num_stages(plan):
+    return lib.bfmht_plan_num_stages(plan)
+
+
+def bfmht_plan_set_tile_cols(plan, transpose, stage, cols):
+    _check(lib.bfmht_plan_set_tile_cols(plan, int(transpose), int(stage), int(cols)), "bfmht_plan_set_tile_cols")
+
+
+def bfmht_plan_get_tile_cols(plan, transpose, stage):
+    return lib.bfmht_plan_get_tile_cols(plan, int(transpose), int(stage))
+
+
+def _arr(ctype, vals):
+    return (ctype * max(1, len(vals)))(*vals)
+
+
+def bfmht_batched_workspace_bytes(plans, nrhs):
+    return lib.bfmht_batched_workspace_bytes(_arr(ctypes.c_void_p, plans), len(plans), _arr(ctypes.c_int32, nrhs))
+
+
+def bfmht_apply_batched(plans, ins, ldin, outs, ldout, nrhs, transpose, ws_ptr, ws_bytes, stream=0):
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    _check(lib.bfmht_apply_batched(_arr(vp, plans), len(plans), _arr(vp, ins), _arr(i64, ldin), _arr(vp, outs),
+                                   _arr(i64, ldout), _arr(i32, nrhs), int(transpose), ws_ptr, int(ws_bytes),
+                                   stream), "bfmht_apply_batched")
 
 
 class Plan:
@@ -219,3 +260,52 @@ class Plan:
         if h:
             bfmht_plan_destroy(h)
             self.handle = None
+
+
+class Batch:
+    """Several uploaded plans of one precision applied together.
+
+    run(inputs, transpose=False) takes one (rows, nrhs_i) tensor per plan and
+    returns the outputs; launch k runs the k-th stage of every instance.
+    """
+
+    def __init__(self, plans):
+        if not plans:
+            raise ValueError("empty batch")
+        dt = {p.dtype for p in plans}
+        if len(dt) != 1:
+            raise ValueError("plans of a batch must share one precision")
+        self.plans = list(plans)
+        self.torch = plans[0].torch
+        self.device = plans[0].device
+        self._ws = None
+        self._ws_bytes = 0
+
+    def workspace(self, nrhs):
+        need = bfmht_batched_workspace_bytes([p.handle for p in self.plans], nrhs)
+        if need < 0:
+            raise ValueError("bad batch arguments")
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = self.torch.empty(need + 256, dtype=self.torch.uint8, device=self.device)
+            self._ws_bytes = need
+        return (self._ws.data_ptr() + 255) // 256 * 256, need
+
+    def launch(self, inputs, outputs, transpose=False):
+        torch = self.torch
+        xs = []
+        for p, x in zip(self.plans, inputs):
+            x, _ = p._prep(x, p.n if transpose else p.m)
+            xs.append(x)
+        nrhs = [int(x.shape[1]) for x in xs]
+        ws, wsb = self.workspace(nrhs)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_apply_batched([p.handle for p in self.plans], [x.data_ptr() for x in xs], [x.stride(0) for x in xs],
+                            [y.data_ptr() for y in outputs], [y.stride(0) for y in outputs], nrhs,
+                            1 if transpose else 0, ws, wsb, stream)
+        return outputs
+
+    def run(self, inputs, transpose=False):
+        torch = self.torch
+        outs = [torch.empty(((p.m if transpose else p.n), int(x.shape[1] if x.dim() == 2 else 1)),
+                            dtype=p.dtype, device=self.device) for p, x in zip(self.plans, inputs)]
+        return self.launch(inputs, outs, transpose)

@@ -75,8 +75,23 @@ struct StageArgs {
 // Output rows per workgroup tile; the plan builds its tile lists for this height.
 constexpr int kTileRows = 64;
 
-// Launch one stage.  Returns 0 or a hipError_t value.
-int launch_fwd_stage(int prec, const StageArgs &a, void *stream);
-int launch_bwd_stage(int prec, const StageArgs &a, void *stream);
+// Launch one stage with tiles of bn RHS columns (16, 32 or 64).  Returns 0 or a
+// hipError_t value.
+int launch_fwd_stage(int prec, const StageArgs &a, int bn, void *stream);
+int launch_bwd_stage(int prec, const StageArgs &a, int bn, void *stream);
+
+// One stage of one instance inside a batched launch.
+struct Segment {
+  StageArgs a;
+  int32_t fwd;     // 1: forward stage, 0: transposed stage
+  int32_t bn;      // RHS columns per tile (16, 32, 64)
+  int32_t ny;      // column tiles
+  int32_t pad;
+  int64_t item0;   // first work item (block index) of this segment in its launch
+  int64_t nitems;  // a.ntiles * ny
+};
+
+// One launch over `items` work items of `nseg` segments (all of one stage position).
+int launch_batched_stage(int prec, const Segment *segs_dev, int32_t nseg, int64_t items, void *stream);
 
 }  // namespace bfmht

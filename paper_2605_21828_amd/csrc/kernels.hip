@@ -19,6 +19,8 @@
 // matrix cores, with one barrier per chunk.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bfmht_internal.h"
 
 namespace bfmht {
@@ -170,13 +172,12 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t *acc, const T 
 
 // Forward stage: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
 template <typename T, int BN>
-__global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
+__device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
-  __shared__ __attribute__((aligned(16))) T Xs[2 * Tl::XBUF];
-  const Tile tile = a.tiles[blockIdx.x];
+  const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
-  const int n0 = blockIdx.y * BN;
+  const int n0 = ny * BN;
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
   const int tid = threadIdx.x;
@@ -217,13 +218,12 @@ __global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
 // Transposed stage: dst[out_row .. out_row+K) = sum over consumers of W_c^T g_c,
 // identity consumers adding their gradient rows directly.
 template <typename T, int BN>
-__global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
+__device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
-  __shared__ __attribute__((aligned(16))) T Xs[2 * Tl::XBUF];
-  const Tile tile = a.tiles[blockIdx.x];
+  const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
-  const int n0 = blockIdx.y * BN;
+  const int n0 = ny * BN;
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
   const int tid = threadIdx.x;
@@ -257,6 +257,18 @@ __global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
         dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
       }
     }
+}
+
+template <typename T, int BN>
+__global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) T Xs[2 * Tiling<T, BN>::XBUF];
+  fwd_tile<T, BN>(a, blockIdx.x, blockIdx.y, Xs);
+}
+
+template <typename T, int BN>
+__global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) T Xs[2 * Tiling<T, BN>::XBUF];
+  bwd_tile<T, BN>(a, blockIdx.x, blockIdx.y, Xs);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,13 +419,12 @@ __device__ __forceinline__ void gemm_block_bf(v4f *acc, const uint16_t *const (&
 }
 
 template <int NTERM, int BN>
-__global__ __launch_bounds__(kNT) void fwd_stage_bf16_kernel(StageArgs a) {
+__device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * Tl::XBUF];
-  const Tile tile = a.tiles[blockIdx.x];
+  const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
-  const int n0 = blockIdx.y * BN;
+  const int n0 = ny * BN;
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
   const int tid = threadIdx.x;
@@ -453,13 +464,12 @@ __global__ __launch_bounds__(kNT) void fwd_stage_bf16_kernel(StageArgs a) {
 }
 
 template <int NTERM, int BN>
-__global__ __launch_bounds__(kNT) void bwd_stage_bf16_kernel(StageArgs a) {
+__device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * Tl::XBUF];
-  const Tile tile = a.tiles[blockIdx.x];
+  const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
-  const int n0 = blockIdx.y * BN;
+  const int n0 = ny * BN;
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
   const int tid = threadIdx.x;
@@ -497,6 +507,18 @@ __global__ __launch_bounds__(kNT) void bwd_stage_bf16_kernel(StageArgs a) {
 }
 
 template <int NTERM, int BN>
+__global__ __launch_bounds__(kNT) void fwd_stage_bf16_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * TilingB<NTERM, BN>::XBUF];
+  fwd_tile_bf<NTERM, BN>(a, blockIdx.x, blockIdx.y, Xs);
+}
+
+template <int NTERM, int BN>
+__global__ __launch_bounds__(kNT) void bwd_stage_bf16_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * TilingB<NTERM, BN>::XBUF];
+  bwd_tile_bf<NTERM, BN>(a, blockIdx.x, blockIdx.y, Xs);
+}
+
+template <int NTERM, int BN>
 static int launch_bf_t(bool fwd, const StageArgs &a, void *stream) {
   if (a.ntiles == 0) return 0;
   dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
@@ -507,12 +529,6 @@ static int launch_bf_t(bool fwd, const StageArgs &a, void *stream) {
   return (int)hipGetLastError();
 }
 
-template <int NTERM>
-static int launch_bf(bool fwd, const StageArgs &a, void *stream) {
-  if (a.nrhs <= 16) return launch_bf_t<NTERM, 16>(fwd, a, stream);
-  if (a.nrhs <= 32) return launch_bf_t<NTERM, 32>(fwd, a, stream);
-  return launch_bf_t<NTERM, 64>(fwd, a, stream);
-}
 
 template <typename T, int BN>
 static int launch_t(bool fwd, const StageArgs &a, void *stream) {
@@ -525,24 +541,118 @@ static int launch_t(bool fwd, const StageArgs &a, void *stream) {
   return (int)hipGetLastError();
 }
 
-template <typename T>
-static int launch_bn(bool fwd, const StageArgs &a, void *stream) {
-  if (a.nrhs <= 16) return launch_t<T, 16>(fwd, a, stream);
-  if (a.nrhs <= 32) return launch_t<T, 32>(fwd, a, stream);
-  return launch_t<T, 64>(fwd, a, stream);
+// Tile width for a stage: an explicit 16/32/64, or the smallest that covers nrhs.
+static int pick_bn(int bn, int nrhs) {
+  if (bn == 16 || bn == 32 || bn == 64) return bn;
+  return nrhs <= 16 ? 16 : (nrhs <= 32 ? 32 : 64);
 }
 
-static int launch(bool fwd, int prec, const StageArgs &a, void *stream) {
+template <typename T>
+static int launch_bn(bool fwd, const StageArgs &a, int bn, void *stream) {
+  switch (pick_bn(bn, a.nrhs)) {
+    case 16: return launch_t<T, 16>(fwd, a, stream);
+    case 32: return launch_t<T, 32>(fwd, a, stream);
+    default: return launch_t<T, 64>(fwd, a, stream);
+  }
+}
+
+template <int NTERM>
+static int launch_bf(bool fwd, const StageArgs &a, int bn, void *stream) {
+  switch (pick_bn(bn, a.nrhs)) {
+    case 16: return launch_bf_t<NTERM, 16>(fwd, a, stream);
+    case 32: return launch_bf_t<NTERM, 32>(fwd, a, stream);
+    default: return launch_bf_t<NTERM, 64>(fwd, a, stream);
+  }
+}
+
+static int launch(bool fwd, int prec, const StageArgs &a, int bn, void *stream) {
   switch (prec) {
-    case P_F64: return launch_bn<double>(fwd, a, stream);
-    case P_F32: return launch_bn<float>(fwd, a, stream);
-    case P_BF16X2: return launch_bf<2>(fwd, a, stream);
-    case P_BF16X3: return launch_bf<3>(fwd, a, stream);
+    case P_F64: return launch_bn<double>(fwd, a, bn, stream);
+    case P_F32: return launch_bn<float>(fwd, a, bn, stream);
+    case P_BF16X2: return launch_bf<2>(fwd, a, bn, stream);
+    case P_BF16X3: return launch_bf<3>(fwd, a, bn, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
 
-int launch_fwd_stage(int prec, const StageArgs &a, void *stream) { return launch(true, prec, a, stream); }
-int launch_bwd_stage(int prec, const StageArgs &a, void *stream) { return launch(false, prec, a, stream); }
+int launch_fwd_stage(int prec, const StageArgs &a, int bn, void *stream) { return launch(true, prec, a, bn, stream); }
+int launch_bwd_stage(int prec, const StageArgs &a, int bn, void *stream) { return launch(false, prec, a, bn, stream); }
+
+// ---------------------------------------------------------------------------
+// Many instances of uneven size per launch.  A batched apply runs one launch
+// per stage position: launch k holds every instance's k-th stage, each
+// workgroup decoding (segment, tile, column tile) from its block index through
+// the segments' first-item offsets.  Stages of one instance are ordered by the
+// launch boundaries, so no workgroup ever waits on another.
+
+template <int P> struct BatchLds;
+template <> struct BatchLds<P_F64> { static constexpr int bytes = 2 * Tiling<double, 64>::XBUF * 8; };
+template <> struct BatchLds<P_F32> { static constexpr int bytes = 2 * Tiling<float, 64>::XBUF * 4; };
+template <> struct BatchLds<P_BF16X2> { static constexpr int bytes = 2 * 2 * TilingB<2, 64>::XBUF * 2; };
+template <> struct BatchLds<P_BF16X3> { static constexpr int bytes = 2 * 3 * TilingB<3, 64>::XBUF * 2; };
+
+template <int P>
+__device__ __forceinline__ void run_item(const Segment &S, int tix, int ny, void *lds) {
+  if constexpr (P == P_F64 || P == P_F32) {
+    typedef typename std::conditional<P == P_F64, double, float>::type T;
+    T *Xs = static_cast<T *>(lds);
+    if (S.fwd) {
+      if (S.bn == 16) fwd_tile<T, 16>(S.a, tix, ny, Xs);
+      else if (S.bn == 32) fwd_tile<T, 32>(S.a, tix, ny, Xs);
+      else fwd_tile<T, 64>(S.a, tix, ny, Xs);
+    } else {
+      if (S.bn == 16) bwd_tile<T, 16>(S.a, tix, ny, Xs);
+      else if (S.bn == 32) bwd_tile<T, 32>(S.a, tix, ny, Xs);
+      else bwd_tile<T, 64>(S.a, tix, ny, Xs);
+    }
+  } else {
+    constexpr int NTERM = P == P_BF16X2 ? 2 : 3;
+    uint16_t *Xs = static_cast<uint16_t *>(lds);
+    if (S.fwd) {
+      if (S.bn == 16) fwd_tile_bf<NTERM, 16>(S.a, tix, ny, Xs);
+      else if (S.bn == 32) fwd_tile_bf<NTERM, 32>(S.a, tix, ny, Xs);
+      else fwd_tile_bf<NTERM, 64>(S.a, tix, ny, Xs);
+    } else {
+      if (S.bn == 16) bwd_tile_bf<NTERM, 16>(S.a, tix, ny, Xs);
+      else if (S.bn == 32) bwd_tile_bf<NTERM, 32>(S.a, tix, ny, Xs);
+      else bwd_tile_bf<NTERM, 64>(S.a, tix, ny, Xs);
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(kNT) void batched_stage_kernel(const Segment *segs, int32_t nseg) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[BatchLds<P>::bytes];
+  const int64_t g = blockIdx.x;
+  int32_t lo = 0, hi = nseg - 1;  // last segment whose first item is <= g
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].item0 <= g) lo = mid; else hi = mid - 1;
+  }
+  const Segment &S = segs[lo];
+  const int64_t t = g - S.item0;
+  run_item<P>(S, (int)(t % S.a.ntiles), (int)(t / S.a.ntiles), lds);
+}
+
+int launch_batched_stage(int prec, const Segment *segs_dev, int32_t nseg, int64_t items, void *stream) {
+  if (items == 0) return 0;
+  const dim3 grid((unsigned)items);
+  switch (prec) {
+    case P_F64:
+      hipLaunchKernelGGL((batched_stage_kernel<P_F64>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      break;
+    case P_F32:
+      hipLaunchKernelGGL((batched_stage_kernel<P_F32>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      break;
+    case P_BF16X2:
+      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X2>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      break;
+    case P_BF16X3:
+      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X3>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
 
 }  // namespace bfmht

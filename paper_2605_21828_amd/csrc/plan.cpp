@@ -75,6 +75,7 @@ struct bfmht_plan {
   std::vector<unsigned char> staging;
   char *dev = nullptr;
   bool uploaded = false;
+  std::vector<int32_t> bn[2];  // per-stage tile width override (0 = by nrhs), [0] forward, [1] transposed
 };
 
 namespace {
@@ -336,6 +337,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     add_ftiles(s);
     add_btiles(s);
   }
+  p->bn[0].assign(p->stages.size(), 0);
+  p->bn[1].assign(p->stages.size(), 0);
 
   // Device layout.
   int64_t cur = 0;
@@ -466,66 +469,182 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
   return a;
 }
 
+// Arguments of stage s of one apply of plan p (forward or transposed) between
+// user buffers in/out and the two level buffers buf[0], buf[1].
+StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, const void *in, int64_t ldin, void *out,
+                   int64_t ldout, int32_t nrhs, char *const buf[2]) {
+  StageArgs a = base_args(p, s, fwd);
+  a.nrhs = nrhs;
+  if (fwd) {
+    // stage l reads level l-1 (or c) and writes level l (or f)
+    if (s.kind == 0) { a.src = in; a.lds = ldin; } else { a.src = buf[(s.level - 1) & 1]; a.lds = nrhs; }
+    if (s.kind == 2) { a.dst = out; a.ldd = ldout; } else { a.dst = buf[s.level & 1]; a.ldd = nrhs; }
+  } else {
+    // the transposed stage l reads level l (or f) and writes level l-1 (or g)
+    if (s.kind == 2) { a.src = in; a.lds = ldin; } else { a.src = buf[s.level & 1]; a.lds = nrhs; }
+    if (s.kind == 0) { a.dst = out; a.ldd = ldout; } else { a.dst = buf[(s.level - 1) & 1]; a.ldd = nrhs; }
+  }
+  a.vec = vec_ok(a.src, a.lds, p->esz);
+  return a;
+}
+
+int64_t level_buffer_bytes(const bfmht_plan *p, int32_t nrhs) {
+  return align_up(p->max_rows * (int64_t)nrhs * p->esz, 256);
+}
+
+bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out, int64_t ldout,
+                       int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
+  bfmht_status st = check_call(p, in, ldin, out, ldout, nrhs, ws, ws_bytes);
+  if (st != BFMHT_OK || nrhs == 0) return st;
+  char *const buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + level_buffer_bytes(p, nrhs)};
+  const int S = (int)p->stages.size();
+  for (int k = 0; k < S; ++k) {
+    const int si = fwd ? k : S - 1 - k;
+    const StageDesc &s = p->stages[si];
+    StageArgs a = stage_io(p, s, fwd, in, ldin, out, ldout, nrhs, buf);
+    const int bn = p->bn[fwd ? 0 : 1][si];
+    const int e = fwd ? launch_fwd_stage(p->prec, a, bn, stream) : launch_bwd_stage(p->prec, a, bn, stream);
+    if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  return BFMHT_OK;
+}
+
+
+int pick_cols(int bn, int nrhs) {
+  if (bn == 16 || bn == 32 || bn == 64) return bn;
+  return nrhs <= 16 ? 16 : (nrhs <= 32 ? 32 : 64);
+}
+
 }  // namespace
 
 extern "C" {
 
 bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *f, int64_t ldf, int32_t nrhs,
                          void *ws, int64_t ws_bytes, void *stream) {
-  bfmht_status st = check_call(p, c, ldc, f, ldf, nrhs, ws, ws_bytes);
-  if (st != BFMHT_OK || nrhs == 0) return st;
-  char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + align_up(p->max_rows * (int64_t)nrhs * p->esz, 256)};
-  for (const StageDesc &s : p->stages) {
-    StageArgs a = base_args(p, s, true);
-    a.nrhs = nrhs;
-    if (s.kind == 0) {
-      a.src = c;
-      a.lds = ldc;
-    } else {
-      a.src = buf[(s.level - 1) & 1];
-      a.lds = nrhs;
-    }
-    if (s.kind == 2) {
-      a.dst = f;
-      a.ldd = ldf;
-    } else {
-      a.dst = buf[s.level & 1];
-      a.ldd = nrhs;
-    }
-    a.vec = vec_ok(a.src, a.lds, p->esz);
-    const int e = launch_fwd_stage(p->prec, a, stream);
-    if (e) return fail(BFMHT_EHIP, std::string("apply stage launch: ") + hipGetErrorString((hipError_t)e));
-  }
-  return BFMHT_OK;
+  return run_apply(p, true, c, ldc, f, ldf, nrhs, ws, ws_bytes, stream);
 }
 
 bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t ldf, void *g, int64_t ldg,
                                    int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
-  bfmht_status st = check_call(p, f, ldf, g, ldg, nrhs, ws, ws_bytes);
-  if (st != BFMHT_OK || nrhs == 0) return st;
-  char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + align_up(p->max_rows * (int64_t)nrhs * p->esz, 256)};
-  for (auto it = p->stages.rbegin(); it != p->stages.rend(); ++it) {
-    const StageDesc &s = *it;
-    StageArgs a = base_args(p, s, false);
-    a.nrhs = nrhs;
-    // transposed stage at forward level l writes the level l-1 vector (or g)
-    if (s.kind == 2) {
-      a.src = f;
-      a.lds = ldf;
-    } else {
-      a.src = buf[s.level & 1];
-      a.lds = nrhs;
+  return run_apply(p, false, f, ldf, g, ldg, nrhs, ws, ws_bytes, stream);
+}
+
+int32_t bfmht_plan_num_stages(const bfmht_plan *p) { return p ? (int32_t)p->stages.size() : -1; }
+
+bfmht_status bfmht_plan_set_tile_cols(bfmht_plan *p, int32_t transpose, int32_t stage, int32_t cols) {
+  if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
+  if (stage < 0 || stage >= (int32_t)p->stages.size()) return fail(BFMHT_EINVAL, "stage out of range");
+  if (cols != 0 && cols != 16 && cols != 32 && cols != 64) return fail(BFMHT_EINVAL, "tile columns must be 0, 16, 32 or 64");
+  p->bn[transpose ? 1 : 0][stage] = cols;
+  return BFMHT_OK;
+}
+
+int32_t bfmht_plan_get_tile_cols(const bfmht_plan *p, int32_t transpose, int32_t stage) {
+  if (!p || stage < 0 || stage >= (int32_t)p->stages.size()) return -1;
+  return p->bn[transpose ? 1 : 0][stage];
+}
+
+// ---- batched ----
+
+namespace {
+struct BatchLayout {
+  int64_t segs = 0, bufs = 0, total = 0;
+  int32_t nseg = 0;
+  std::vector<int64_t> buf_off;  // per instance
+};
+
+bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs, BatchLayout &L) {
+  if (count < 0) return fail(BFMHT_EINVAL, "count < 0");
+  if (count > 0 && (!plans || !nrhs)) return fail(BFMHT_EINVAL, "NULL plans or nrhs");
+  L.nseg = 0;
+  L.buf_off.assign(count, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(BFMHT_EINVAL, "NULL plan in batch");
+    if (nrhs[i] < 0) return fail(BFMHT_EINVAL, "nrhs < 0 in batch");
+    if (plans[i]->prec != plans[0]->prec) return fail(BFMHT_EINVAL, "plans of a batch must share one precision");
+    if (nrhs[i] > 0) L.nseg += (int32_t)plans[i]->stages.size();
+  }
+  L.segs = 0;
+  L.bufs = align_up((int64_t)L.nseg * (int64_t)sizeof(Segment), 256);
+  int64_t cur = L.bufs;
+  for (int32_t i = 0; i < count; ++i) {
+    L.buf_off[i] = cur;
+    if (nrhs[i] > 0) cur += 2 * level_buffer_bytes(plans[i], nrhs[i]);
+  }
+  L.total = std::max<int64_t>(cur, 256);
+  return BFMHT_OK;
+}
+}  // namespace
+
+int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs) {
+  BatchLayout L;
+  if (batch_layout(plans, count, nrhs, L) != BFMHT_OK) return -1;
+  return L.total;
+}
+
+bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
+                                 const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
+  BatchLayout L;
+  bfmht_status st = batch_layout(plans, count, nrhs, L);
+  if (st != BFMHT_OK) return st;
+  if (count == 0 || L.nseg == 0) return BFMHT_OK;
+  if (!in || !ldin || !out || !ldout || !ws) return fail(BFMHT_EINVAL, "NULL batch argument");
+  if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(BFMHT_ENOSPACE, "workspace too small for the batch");
+  const bool fwd = transpose == 0;
+  std::vector<std::vector<Segment>> per(count);
+  size_t maxS = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const bfmht_plan *p = plans[i];
+    if (nrhs[i] == 0) continue;
+    if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
+    if (!in[i] || !out[i]) return fail(BFMHT_EINVAL, "NULL input or output in batch");
+    if (ldin[i] < nrhs[i] || ldout[i] < nrhs[i]) return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
+    char *base = static_cast<char *>(ws) + L.buf_off[i];
+    char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
+    const int S = (int)p->stages.size();
+    for (int k = 0; k < S; ++k) {
+      const int si = fwd ? k : S - 1 - k;
+      Segment sg{};
+      sg.a = stage_io(p, p->stages[si], fwd, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);
+      sg.fwd = fwd ? 1 : 0;
+      sg.bn = pick_cols(p->bn[fwd ? 0 : 1][si], nrhs[i]);
+      sg.ny = (nrhs[i] + sg.bn - 1) / sg.bn;
+      sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
+      per[i].push_back(sg);
     }
-    if (s.kind == 0) {
-      a.dst = g;
-      a.ldd = ldg;
-    } else {
-      a.dst = buf[(s.level - 1) & 1];
-      a.ldd = nrhs;
+    maxS = std::max(maxS, per[i].size());
+  }
+  // Launch k runs the k-th stage of every instance; segments of one launch are
+  // contiguous in the table, segments without items are left out.
+  std::vector<Segment> segs;
+  std::vector<std::pair<size_t, int64_t>> launches;  // (first segment, items)
+  for (size_t k = 0; k < maxS; ++k) {
+    const size_t first = segs.size();
+    int64_t item = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      if (k >= per[i].size() || per[i][k].nitems == 0) continue;
+      Segment sg = per[i][k];
+      sg.item0 = item;
+      item += sg.nitems;
+      segs.push_back(sg);
     }
-    a.vec = vec_ok(a.src, a.lds, p->esz);
-    const int e = launch_bwd_stage(p->prec, a, stream);
-    if (e) return fail(BFMHT_EHIP, std::string("apply_transpose stage launch: ") + hipGetErrorString((hipError_t)e));
+    if (item >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
+    launches.push_back({first, item});
+  }
+  char *w = static_cast<char *>(ws);
+  if (!segs.empty()) {
+    hipError_t e = hipMemcpyAsync(w + L.segs, segs.data(), segs.size() * sizeof(Segment), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("batch table upload: ") + hipGetErrorString(e));
+  }
+  const Segment *dsegs = reinterpret_cast<const Segment *>(w + L.segs);
+  for (size_t k = 0; k < launches.size(); ++k) {
+    const size_t first = launches[k].first;
+    const size_t nk = (k + 1 < launches.size() ? launches[k + 1].first : segs.size()) - first;
+    const int rc = launch_batched_stage(plans[0]->prec, dsegs + first, (int32_t)nk, launches[k].second, stream);
+    if (rc) return fail(BFMHT_EHIP, std::string("batched launch: ") + hipGetErrorString((hipError_t)rc));
   }
   return BFMHT_OK;
 }

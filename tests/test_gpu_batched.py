@@ -1,0 +1,119 @@
+"""Batched multi-instance apply and per-stage tile widths (GPU, through the C ABI)."""
+import numpy as np
+import pytest
+
+from factor_gen import random_factor_set
+from oracle import butterfly as ob
+from oracle import dense as od
+from oracle import modes as om
+from paper_2605_21828_amd import workloads as wl
+from paper_2605_21828_amd.factor import io as fio
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # seed, n, m, L, max_rank, nrhs
+    (60, 300, 200, 4, 40, 1),
+    (61, 1000, 333, 5, 90, 5),
+    (62, 77, 500, 3, 130, 17),
+    (63, 257, 129, 7, 20, 33),
+    (64, 5, 3, 2, 4, 64),
+    (65, 640, 640, 6, 70, 100),
+    (66, 90, 60, 3, 30, 0),      # skipped instance
+]
+
+
+def _dt(prec):
+    import torch
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _t(x, dt):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def _np(x):
+    import torch
+    torch.cuda.synchronize()
+    return x.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def instances():
+    return [random_factor_set(s, n, m, L, max_rank=r) for s, n, m, L, r, _ in CASES]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16x3", 1e-5)])
+def test_batched_matches_oracle(gpu, instances, prec, tol):
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    plans = [Plan(fs, prec, max_nrhs=max(1, c[5])) for fs, c in zip(instances, CASES)]
+    rng = np.random.default_rng(7)
+    cs = [rng.standard_normal((int(fs["m"]), c[5])) for fs, c in zip(instances, CASES)]
+    fv = [rng.standard_normal((int(fs["n"]), c[5])) for fs, c in zip(instances, CASES)]
+    batch = Batch(plans)
+    ys = batch.run([_t(c, _dt(prec)) for c in cs])
+    gs = batch.run([_t(f, _dt(prec)) for f in fv], transpose=True)
+    for fs, c, f, y, g, case in zip(instances, cs, fv, ys, gs, CASES):
+        if case[5] == 0:
+            continue
+        assert od.rel_err_cols(_np(y), ob.apply(fs, c))[0] <= tol, case
+        assert od.rel_err_cols(_np(g), ob.apply_transpose(fs, f))[0] <= tol, case
+
+
+def test_batched_equals_single_applies_bitwise(gpu, instances):
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    plans = [Plan(fs, "f32", max_nrhs=max(1, c[5])) for fs, c in zip(instances, CASES)]
+    rng = np.random.default_rng(8)
+    xs = [_t(rng.standard_normal((int(fs["m"]), c[5])), _dt("f32")) for fs, c in zip(instances, CASES)]
+    ys = Batch(plans).run(xs)
+    for p, x, y, c in zip(plans, xs, ys, CASES):
+        if c[5]:
+            assert np.array_equal(_np(p.apply(x)), _np(y))
+
+
+def test_grid_instances_vs_inverse_dft(gpu):
+    """Uniform-grid instances of uneven size in one launch, each against its inverse DFT."""
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    rng = wl.rng(40, 5)
+    sides = [16, 24, 32, 48, 32, 16, 64, 24]
+    plans, cs, refs = [], [], []
+    for i, N in enumerate(sides):
+        n, m = N * N, N * N // 4
+        fs, _ = fio.fourier_factors(wl.grid_points(N), m, 64, 1e-8, workers=4, cache=False)
+        b = int(rng.integers(1, 129))
+        c = wl.coefficients(400 + i, m, b)
+        plans.append(Plan(fs, "f32", max_nrhs=b))
+        cs.append(c)
+        refs.append(om.grid_synthesis_ifft2(N, om.fourier_modes(m), c))
+    ys = Batch(plans).run([_t(c, _dt("f32")) for c in cs])
+    for y, ref in zip(ys, refs):
+        assert od.rel_err_cols(_np(y), ref)[0] <= 1e-5
+
+
+def test_tile_width_does_not_change_results(gpu, instances):
+    from paper_2605_21828_amd import bfmht as B
+    from paper_2605_21828_amd.bfmht import Plan
+    fs = instances[5]
+    p = Plan(fs, "f32", max_nrhs=100)
+    x = _t(np.random.default_rng(9).standard_normal((int(fs["m"]), 100)), _dt("f32"))
+    f = _t(np.random.default_rng(10).standard_normal((int(fs["n"]), 100)), _dt("f32"))
+    base_y, base_g = _np(p.apply(x)), _np(p.apply_t(f))
+    S = B.bfmht_plan_num_stages(p.handle)
+    assert S == int(fs["L"]) + 2
+    for k in range(S):
+        B.bfmht_plan_set_tile_cols(p.handle, 0, k, (16, 32, 64)[k % 3])
+        B.bfmht_plan_set_tile_cols(p.handle, 1, k, (64, 16, 32)[k % 3])
+    assert B.bfmht_plan_get_tile_cols(p.handle, 0, 1) == 32
+    assert np.array_equal(_np(p.apply(x)), base_y)
+    assert np.array_equal(_np(p.apply_t(f)), base_g)
+    with pytest.raises(B.BfmhtError):
+        B.bfmht_plan_set_tile_cols(p.handle, 0, 0, 48)
+    with pytest.raises(B.BfmhtError):
+        B.bfmht_plan_set_tile_cols(p.handle, 0, S, 16)
+
+
+@pytest.mark.skip(reason="single persistent launch with inter-workgroup waits is switched off: two runs "
+                         "stalled past the silence limit inside the stream sync (no fault) and the cause "
+                         "was not shown on the CPU; batched applies use one launch per stage position")
+def test_persistent_single_launch_matches_oracle(gpu):
+    """Kept as a record of the switched-off case; see the design notes on batched launches."""
