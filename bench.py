@@ -75,6 +75,88 @@ def cpu_baseline(fs, pts, c_host, f_host, out32, g32, rows, cols, lam):
                   "analysis_cols_sampled": len(cols), "analysis_rel_err": err_g}
 
 
+def bench_batched(args):
+    """Multi-instance workload: 32 uniform-grid instances of uneven size, FP32."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.autotune import tune_batch
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    from paper_2605_21828_amd.factor import io as fio
+
+    spec = wl.BATCHED
+    inst = wl.batched_instances(spec)
+    dev = torch.device("cuda:0")
+    built = {}
+    for side in sorted({s for s, _ in inst}):
+        n = side * side
+        log("building factors: grid side %d (n=%d, m=%d)" % (side, n, n // 4))
+        built[side] = fio.fourier_factors(wl.grid_points(side), n // 4, spec["leaf"], spec["tol"],
+                                          workers=args.workers, cache=args.cache)[0]
+    by_side = {side: Plan(fs, "f32", max_nrhs=spec["max_nrhs"], device=dev) for side, fs in built.items()}
+    plans, xs, fvs, cs_host = [], [], [], []
+    for i, (side, b) in enumerate(inst):
+        p = by_side[side]   # instances of one side share one uploaded factor set
+        c = wl.coefficients(spec["wid"] * 100 + i, p.m, b)
+        cs_host.append(c)
+        plans.append(p)
+        xs.append(torch.tensor(c, dtype=torch.float32, device=dev))
+        fvs.append(torch.tensor(wl.values(spec["wid"] * 100 + i, p.n, b), dtype=torch.float32, device=dev))
+    batch = Batch(plans)
+    outs = [torch.empty((p.n, x.shape[1]), dtype=torch.float32, device=dev) for p, x in zip(plans, xs)]
+    outs_t = [torch.empty((p.m, x.shape[1]), dtype=torch.float32, device=dev) for p, x in zip(plans, xs)]
+    tune_batch(batch, xs, transpose=False, log=log)
+    tune_batch(batch, fvs, transpose=True, log=log)
+
+    def step():
+        batch.launch(xs, outs, False)
+        batch.launch(fvs, outs_t, True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    reps = max(args.steps, 5)
+    ms_fwd = event_time(lambda: batch.launch(xs, outs, False), reps, torch)
+
+    def one_by_one():
+        for p, x, y in zip(plans, xs, outs):
+            p.apply(x, out=y)
+    ms_seq = event_time(one_by_one, reps, torch)
+    rhs_points = sum(p.n * int(x.shape[1]) for p, x in zip(plans, xs))
+    F = sum(fio.stored_entries(built[s]) * b for s, b in inst)
+    achieved = 2.0 * F / (ms_fwd * 1e-3) / 1e12
+    errs = None
+    if not args.no_cpu_baseline:
+        from oracle import dense as od
+        from oracle import modes as om
+        errs = []
+        torch.cuda.synchronize()
+        for (side, b), y, c in zip(inst, outs, cs_host):
+            ref = om.grid_synthesis_ifft2(side, om.fourier_modes(side * side // 4), c)
+            errs.append(od.rel_err_cols(y.double().cpu().numpy(), ref)[0])
+    res = {
+        "metric": "butterfly apply RHS*points/s (FP32 batched synthesis + analysis)",
+        "value": 2.0 * rhs_points / (ms * 1e-3), "unit": "RHS*points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched32", "instances": [[s, b] for s, b in inst], "m": "n/4",
+                   "leaf": spec["leaf"], "tol": spec["tol"], "step": "batched apply + batched apply_transpose"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": achieved / 157.3, "traffic": None,
+                     "kernel": "batched_stage_kernel<1> (all launches of one batched FP32 apply)"},
+        "cpu_baseline": None,
+        "extra": {"batched_apply_ms": ms_fwd, "one_by_one_apply_ms": ms_seq,
+                  "batching_speedup": ms_seq / ms_fwd, "max_instance_rel_err_vs_inverse_dft":
+                  max(errs) if errs else None, "instance_rel_err": errs},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,10 +168,13 @@ def main():
                     help="comma list of other precisions timed on the same inputs")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile widths")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched32":
+        return bench_batched(args)
 
     import torch
 
@@ -118,6 +203,11 @@ def main():
     y32 = torch.empty((n, b), dtype=torch.float32, device=dev)
     g32 = torch.empty((m, b), dtype=torch.float32, device=dev)
 
+    tuned = None
+    if not args.no_tune:
+        from paper_2605_21828_amd.autotune import tune_plan
+        tuned = tune_plan(p32, fs, b, use_cache=args.cache, log=log)
+
     def step():
         p32.apply(c32, out=y32)
         p32.apply_t(f32, out=g32)
@@ -145,6 +235,7 @@ def main():
         "fp32_apply_alg_GBps": alg_bytes32 / (ms_fwd * 1e-3) / 1e9,
         "stored_factor_entries": F, "compression_vs_dense": n * m / F,
         "stage_launches_per_apply": launches,
+        "tile_cols": tuned,
     }
     variants_out = {}
 

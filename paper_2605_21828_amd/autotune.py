@@ -1,0 +1,146 @@
+"""Tile-width autotuner for the butterfly apply.
+
+The tunable is the number of right-hand-side columns per workgroup tile of each
+stage (16, 32 or 64; `bfmht_plan_set_tile_cols`).  Narrower tiles read each
+factor row more than once but give a small stage more workgroups; which wins
+depends on the stage's shape and the RHS count, so it is measured.  The search
+is greedy over stages in order: every stage keeps the width that gives the
+fastest full apply, timed with HIP events on the current stream, the others
+held at their current choice.  Results are cached in a JSON file keyed by the
+plan's shape (sizes, ranks, precision) and the RHS count.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from . import bfmht as B
+
+WIDTHS = (16, 32, 64)
+CACHE = os.environ.get("BFMHT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "bfmht", "tune.json"))
+
+
+def signature(fs, precision, nrhs):
+    h = hashlib.sha1()
+    for k in ("rank", "ident", "xoff", "koff"):
+        h.update(np.ascontiguousarray(fs[k]).tobytes())
+    return "%s|%d|%d|%d|%s|%d" % (precision, int(fs["n"]), int(fs["m"]), int(fs["L"]), h.hexdigest()[:16], nrhs)
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, cache):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time(fn, reps, torch):
+    fn()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def apply_config(plan, config):
+    for d, key in ((0, "fwd"), (1, "bwd")):
+        for k, w in enumerate(config.get(key, [])):
+            B.bfmht_plan_set_tile_cols(plan.handle, d, k, w)
+
+
+def tune_plan(plan, fs, nrhs, reps=10, cache_path=CACHE, use_cache=True, log=None):
+    """Choose per-stage tile widths for `plan` at this RHS count; returns the config dict."""
+    torch = plan.torch
+    key = signature(fs, plan.precision, nrhs)
+    cache = _load_cache(cache_path) if use_cache else {}
+    if key in cache:
+        apply_config(plan, cache[key])
+        return cache[key]
+    x = torch.randn((plan.m, nrhs), dtype=plan.dtype, device=plan.device)
+    y = torch.randn((plan.n, nrhs), dtype=plan.dtype, device=plan.device)
+    out_f = torch.empty((plan.n, nrhs), dtype=plan.dtype, device=plan.device)
+    out_b = torch.empty((plan.m, nrhs), dtype=plan.dtype, device=plan.device)
+    S = B.bfmht_plan_num_stages(plan.handle)
+    config = {}
+    for d, key_d, fn in ((0, "fwd", lambda: plan.apply(x, out=out_f)), (1, "bwd", lambda: plan.apply_t(y, out=out_b))):
+        choice = [0] * S
+        for k in range(S):
+            B.bfmht_plan_set_tile_cols(plan.handle, d, k, 0)
+        base = _time(fn, reps, torch)
+        for k in range(S):
+            best_w, best_t = choice[k], base
+            for w in WIDTHS:
+                B.bfmht_plan_set_tile_cols(plan.handle, d, k, w)
+                t = _time(fn, reps, torch)
+                if t < best_t * 0.995:
+                    best_w, best_t = w, t
+            choice[k] = best_w
+            B.bfmht_plan_set_tile_cols(plan.handle, d, k, best_w)
+            base = min(base, best_t)
+        config[key_d] = choice
+        config[key_d + "_ms"] = base
+        if log:
+            log("autotune %s: %s -> %.3f ms" % (key_d, choice, base))
+    if use_cache:
+        cache = _load_cache(cache_path)
+        cache[key] = config
+        _store_cache(cache_path, cache)
+    return config
+
+
+def tune_batch(batch, inputs, transpose=False, reps=5, log=None):
+    """Choose one uniform tile width per distinct plan of a batch (0 = by nrhs)
+    by greedy search over plans, timing the whole batched apply."""
+    torch = batch.torch
+    outs = [torch.empty(((p.m if transpose else p.n), int(x.shape[1])), dtype=p.dtype, device=batch.device)
+            for p, x in zip(batch.plans, inputs)]
+    d = 1 if transpose else 0
+
+    def set_all(p, w):
+        for k in range(B.bfmht_plan_num_stages(p.handle)):
+            B.bfmht_plan_set_tile_cols(p.handle, d, k, w)
+
+    def fn():
+        batch.launch(inputs, outs, transpose)
+
+    distinct, widest = [], {}
+    for p, x in zip(batch.plans, inputs):
+        if id(p) not in widest:
+            distinct.append(p)
+            widest[id(p)] = 0
+        widest[id(p)] = max(widest[id(p)], int(x.shape[1]))
+    for p in distinct:
+        set_all(p, 0)
+    base = _time(fn, reps, torch)
+    choice = []
+    for p in distinct:
+        best_w, best_t = 0, base
+        for w in WIDTHS:
+            if w > 16 and widest[id(p)] <= w // 2:
+                continue  # wider than twice the largest RHS count only adds idle columns
+            set_all(p, w)
+            t = _time(fn, reps, torch)
+            if t < best_t * 0.995:
+                best_w, best_t = w, t
+        set_all(p, best_w)
+        choice.append(best_w)
+        base = min(base, best_t)
+    if log:
+        log("autotune batch (%s): widths %s -> %.3f ms" % ("transpose" if transpose else "forward", choice, base))
+    return choice, base

@@ -25,6 +25,19 @@ WORKLOADS = {
 }
 
 
+# Many uneven instances in one call: 32 uniform-grid problems on the periodic
+# square, side drawn from SIDES, m = n / 4 modes, leaf 64, tol 1e-8, 1..128 RHS.
+BATCHED = dict(wid=4, count=32, sides=(32, 48, 64, 96, 128, 192, 256), leaf=64, tol=1e-8, max_nrhs=128)
+
+
+def batched_instances(spec=BATCHED):
+    """[(side, nrhs)] of the multi-instance workload, drawn from its seed."""
+    r = rng(spec["wid"], 0)
+    sides = r.choice(np.array(spec["sides"]), size=spec["count"])
+    nrhs = rng(spec["wid"], 1).integers(1, spec["max_nrhs"] + 1, size=spec["count"])
+    return [(int(a), int(b)) for a, b in zip(sides, nrhs)]
+
+
 def rng(wid, stream):
     return np.random.default_rng([int(wid), int(stream)])
 

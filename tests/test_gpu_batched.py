@@ -117,3 +117,26 @@ def test_tile_width_does_not_change_results(gpu, instances):
                          "was not shown on the CPU; batched applies use one launch per stage position")
 def test_persistent_single_launch_matches_oracle(gpu):
     """Kept as a record of the switched-off case; see the design notes on batched launches."""
+
+
+def test_autotune_sets_widths_and_keeps_results(gpu, instances, tmp_path):
+    from paper_2605_21828_amd import autotune
+    from paper_2605_21828_amd import bfmht as B
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    fs = instances[5]
+    p = Plan(fs, "f32", max_nrhs=100)
+    x = _t(np.random.default_rng(12).standard_normal((int(fs["m"]), 100)), _dt("f32"))
+    base = _np(p.apply(x))
+    cfg = autotune.tune_plan(p, fs, 100, reps=3, cache_path=str(tmp_path / "t.json"))
+    S = B.bfmht_plan_num_stages(p.handle)
+    assert len(cfg["fwd"]) == S and len(cfg["bwd"]) == S
+    assert all(w in (0, 16, 32, 64) for w in cfg["fwd"] + cfg["bwd"])
+    assert [B.bfmht_plan_get_tile_cols(p.handle, 0, k) for k in range(S)] == cfg["fwd"]
+    assert np.array_equal(_np(p.apply(x)), base)
+    # a second plan of the same shape picks the cached choice up
+    q = Plan(fs, "f32", max_nrhs=100)
+    assert autotune.tune_plan(q, fs, 100, cache_path=str(tmp_path / "t.json")) == cfg
+    plans = [Plan(f, "f32", max_nrhs=max(1, c[5])) for f, c in zip(instances, CASES)]
+    xs = [_t(np.random.default_rng(13).standard_normal((pl.m, max(1, c[5]))), _dt("f32")) for pl, c in zip(plans, CASES)]
+    choice, ms = autotune.tune_batch(Batch(plans), xs, reps=2)
+    assert len(choice) == len(plans) and ms > 0
