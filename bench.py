@@ -32,6 +32,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload):
+    """HBM bytes per forward FP32 stage launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or
+    None when the kernels have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.json" % workload)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        with open(os.path.join(ROOT, "paper_2605_21828_amd", "csrc", "kernels.hip"), "rb") as f:
+            cur = hashlib.sha1(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if d.get("kernels_hip_sha1") != cur:
+        return None
+    return d["fwd_per_dispatch"]["hbm_bytes"]
+
+
 def event_time(fn, reps, torch):
     """Average milliseconds of fn() over reps, measured with HIP events on the current stream."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -157,6 +175,20 @@ def bench_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_copy(args):
+    """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = event_time(lambda: dst.copy_(src), 5, torch)
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +207,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched32":
         return bench_batched(args)
+    if args.workload == "copy":
+        return bench_copy(args)
 
     import torch
 
@@ -293,7 +327,9 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
                    "L": int(fs["L"]), "step": "apply + apply_transpose"},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "bytes per launch",
+                     "alg_bytes_per_launch": alg_bytes32 / launches,
                      "kernel": "fwd_stage_kernel<float,64> (all stage launches of one FP32 apply)",
                      "per_launch_alg_flops": flops / launches,
                      "avg_launch_ms": ms_fwd / launches},
