@@ -175,6 +175,88 @@ def bench_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sphere(args):
+    """Perturbed-sphere workload: BF16 split applies with 256 RHS (FP32 and FP64 beside them)."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+
+    spec = wl.SPHERE
+    log("building sphere problem and factors: level %d, m=%d" % (spec["level"], spec["m"]))
+    fs, prob = fio.sphere_factors(spec["level"], spec["wid"], spec["m"], spec["leaf"], spec["tol"],
+                                  workers=args.workers, log=lambda s: log("  ", s), cache=args.cache)
+    Phi = prob["Phi"]
+    n, m, b = Phi.shape[0], Phi.shape[1], spec["nrhs"]
+    F = fio.stored_entries(fs)
+    c = wl.coefficients(spec["wid"], m, b)
+    fv = wl.values(spec["wid"], n, b)
+    dev = torch.device("cuda:0")
+    main = args.precision or "bf16x2"
+    rec = {}
+    outs = {}
+    for prec in [main] + [p for p in ("bf16x3", "bf16x2", "f32", "f64") if p != main]:
+        dt = torch.float64 if prec == "f64" else torch.float32
+        p = Plan(fs, prec, max_nrhs=b, device=dev)
+        ct, ft = torch.tensor(c, dtype=dt, device=dev), torch.tensor(fv, dtype=dt, device=dev)
+        y = torch.empty((n, b), dtype=dt, device=dev)
+        g = torch.empty((m, b), dtype=dt, device=dev)
+
+        def step():
+            p.apply(ct, out=y)
+            p.apply_t(ft, out=g)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        reps = max(args.steps, 5)
+        t_f = event_time(lambda: p.apply(ct, out=y), reps, torch)
+        t_b = event_time(lambda: p.apply_t(ft, out=g), reps, torch)
+        outs[prec] = (y.double().cpu().numpy(), g.double().cpu().numpy())
+        rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b}
+        log("%s step %.3f ms" % (prec, ms))
+        del p, ct, ft, y, g
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        from oracle import butterfly as ob
+        from oracle import dense as od
+        t0 = time.time()
+        ob.apply(fs, c[:, :8])
+        ob.apply_transpose(fs, fv[:, :8])
+        dt_cpu = time.time() - t0
+        ref_y, ref_g = Phi @ c, Phi.T @ fv
+        for prec, (y, g) in outs.items():
+            rec[prec]["synthesis_rel_err_vs_dense_fp64"] = od.rel_err_cols(y, ref_y)[0]
+            rec[prec]["analysis_rel_err_vs_dense_fp64"] = od.rel_err_cols(g, ref_g)[0]
+        base = {"value": 2.0 * n * 8 / dt_cpu, "unit": "RHS*points/s", "cores": os.cpu_count(), "kind": "oracle",
+                "sample": "oracle butterfly apply + transpose (NumPy FP64) on 8 of the 256 RHS, %.1f s" % dt_cpu}
+    else:
+        base = None
+    t_main = rec[main]["apply_ms"]
+    nterm = {"bf16x2": 3, "bf16x3": 6}.get(main, 1)
+    peak = 2500.0 if main.startswith("bf16") else (157.3 if main == "f32" else 78.6)
+    achieved = 2.0 * F * b * nterm / (t_main * 1e-3) / 1e12
+    res = {
+        "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
+        "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec[main]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main, "data": "synthetic",
+        "config": {"workload": "sphere40962", "n": n, "m": m, "nrhs": b, "leaf": spec["leaf"], "tol": spec["tol"],
+                   "L": int(fs["L"]), "step": "apply + apply_transpose"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "note": "executed MFMA flops (split products counted) over the apply"},
+        "cpu_baseline": base,
+        "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "precisions": rec},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_copy(args):
     """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
     import torch
@@ -201,6 +283,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile widths")
+    ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -209,6 +292,8 @@ def main():
         return bench_batched(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "sphere40962":
+        return bench_sphere(args)
 
     import torch
 

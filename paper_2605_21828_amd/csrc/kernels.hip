@@ -78,20 +78,21 @@ struct Tiling {
   static constexpr int XR = KC * BN / kNT;          // RHS values staged per thread per chunk
   static constexpr int XS = KC + XPAD;              // LDS row stride (elements) of the transposed chunk
   static constexpr int XBUF = BN * XS;              // elements per LDS buffer
-  static_assert(XR >= 1 && BN % XR == 0, "staging split");
+  static_assert(XR >= 1 && (kNT / KC) * XR == BN, "staging split: one row per lane, column groups per KC lanes");
 };
 
 // Stage one RHS chunk: rows k0 .. k0+KC of a row-mapped source into registers.
+// Thread t takes row k = t % KC and the XR columns of column group t / KC, so
+// the transposed LDS writes of consecutive lanes hit consecutive addresses.
 template <typename T, int BN>
-__device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t *rowmap, int32_t base, int32_t nrows,
-                                       int k0, int n0, int tid) {
+__device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
+                                       int32_t nrows, int k0, int n0, int tid) {
   typedef Tiling<T, BN> Tl;
-  const int e = tid * Tl::XR;
-  const int k = e / BN, c = e % BN;
+  const int k = tid % Tl::KC, c = (tid / Tl::KC) * Tl::XR;
   const int gk = k0 + k;
 #pragma unroll
   for (int i = 0; i < Tl::XR; ++i) xr[i] = T(0);
-  if (e >= Tl::KC * BN || gk >= nrows) return;
+  if (gk >= nrows) return;
   const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
   const T *p = static_cast<const T *>(a.src) + srow * a.lds + n0 + c;
   if (a.vec && n0 + c + Tl::XR <= a.nrhs) {
@@ -106,9 +107,7 @@ __device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t 
 template <typename T, int BN>
 __device__ __forceinline__ void store_x(T *Xs, const T *xr, int tid) {
   typedef Tiling<T, BN> Tl;
-  const int e = tid * Tl::XR;
-  if (e >= Tl::KC * BN) return;
-  const int k = e / BN, c = e % BN;
+  const int k = tid % Tl::KC, c = (tid / Tl::KC) * Tl::XR;
 #pragma unroll
   for (int i = 0; i < Tl::XR; ++i) Xs[(c + i) * Tl::XS + k] = xr[i];
 }
@@ -301,46 +300,58 @@ struct TilingB {
   static constexpr int FN = BN / 16;
   static constexpr int XS = KC + 8;           // LDS row stride in bf16 (16-byte padding)
   static constexpr int XBUF = BN * XS;        // bf16 per term per buffer
-  static constexpr int XR = KC * BN / kNT;    // RHS values staged per thread per chunk
-  static_assert(XR >= 1 && BN % XR == 0, "staging split");
+  static constexpr int XP = BN / 8;           // columns per thread (32 row pairs x 8 column groups)
+  static constexpr int XR = 2 * XP;           // RHS values staged per thread per chunk
+  static_assert(kNT == 32 * 8 && KC == 64, "staging split: 32 row pairs x 8 column groups");
 };
 
-// Stage one FP32 RHS chunk (rows k0..k0+KC) split into NTERM bf16 terms, transposed.
+// Stage one FP32 RHS chunk (rows k0..k0+KC) split into NTERM bf16 terms,
+// transposed.  Thread t takes rows 2 (t % 32) and 2 (t % 32) + 1 and the XP
+// columns of column group t / 32; the two rows' terms of one column are packed
+// into one 32-bit LDS word, so consecutive lanes write consecutive words.
 template <int NTERM, int BN>
 __device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
                                           int32_t nrows, int k0, int n0, int tid) {
   typedef TilingB<NTERM, BN> Tl;
-  const int e = tid * Tl::XR;
-  const int k = e / BN, c = e % BN;
-  const int gk = k0 + k;
+  const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
 #pragma unroll
-  for (int i = 0; i < Tl::XR; ++i) xr[i] = 0.f;
-  if (gk >= nrows) return;
-  const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
-  const float *p = static_cast<const float *>(a.src) + srow * a.lds + n0 + c;
-  if (a.vec && n0 + c + Tl::XR <= a.nrhs) {
-    copy_vec<float, Tl::XR>(xr, p);
-  } else {
+  for (int i = 0; i < 2 * Tl::XP; ++i) xr[i] = 0.f;
 #pragma unroll
-    for (int i = 0; i < Tl::XR; ++i)
-      if (n0 + c + i < a.nrhs) xr[i] = p[i];
+  for (int h = 0; h < 2; ++h) {
+    const int gk = k0 + k + h;
+    if (gk >= nrows) continue;
+    const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
+    const float *p = static_cast<const float *>(a.src) + srow * a.lds + n0 + c;
+    if (a.vec && n0 + c + Tl::XP <= a.nrhs) {
+      copy_vec<float, Tl::XP>(xr + h * Tl::XP, p);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Tl::XP; ++i)
+        if (n0 + c + i < a.nrhs) xr[h * Tl::XP + i] = p[i];
+    }
   }
 }
 
 template <int NTERM, int BN>
 __device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int tid) {
   typedef TilingB<NTERM, BN> Tl;
-  const int e = tid * Tl::XR;
-  const int k = e / BN, c = e % BN;
+  const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
 #pragma unroll
-  for (int i = 0; i < Tl::XR; ++i) {
-    const float x = xr[i];
-    const uint16_t h = f32_to_bf16_rne(x);
-    const float r = x - bf16_to_f32(h);
-    const uint16_t l = f32_to_bf16_rne(r);
-    Xs[(c + i) * Tl::XS + k] = h;
-    Xs[Tl::XBUF * 2 + (c + i) * Tl::XS + k] = l;
-    if constexpr (NTERM == 3) Xs[Tl::XBUF * 4 + (c + i) * Tl::XS + k] = f32_to_bf16_rne(r - bf16_to_f32(l));
+  for (int i = 0; i < Tl::XP; ++i) {
+    uint32_t w[3] = {0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float x = xr[h * Tl::XP + i];
+      const uint16_t t0 = f32_to_bf16_rne(x);
+      const float r = x - bf16_to_f32(t0);
+      const uint16_t t1 = f32_to_bf16_rne(r);
+      w[0] |= (uint32_t)t0 << (16 * h);
+      w[1] |= (uint32_t)t1 << (16 * h);
+      if constexpr (NTERM == 3) w[2] |= (uint32_t)f32_to_bf16_rne(r - bf16_to_f32(t1)) << (16 * h);
+    }
+#pragma unroll
+    for (int t = 0; t < NTERM; ++t)
+      *reinterpret_cast<uint32_t *>(Xs + t * 2 * Tl::XBUF + (c + i) * Tl::XS + k) = w[t];
   }
 }
 

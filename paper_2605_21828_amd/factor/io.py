@@ -65,3 +65,41 @@ def fourier_factors(points, m, leaf, tol, workers=None, log=None, cache=True, ta
         os.makedirs(CACHE_DIR, exist_ok=True)
         save(path, fs)
     return fs, modes
+
+
+def sphere_factors(level, wid, m, leaf, tol, workers=None, log=None, cache=True):
+    """Build (or load from the cache) the perturbed-sphere problem and its factor set.
+
+    Returns (fs, problem) with problem = dict(v, f, M, lam, Phi).  Space tree:
+    Neumann Fiedler tree on the mesh; frequency tree: index halving on the
+    eigenvalue-sorted columns; both of depth L = ceil(log2(n / leaf)).
+    """
+    from .. import sphere
+    from .mesh_tree import mesh_fiedler_tree
+    tag = "sphere_l%d_w%d_m%d_leaf%d_tol%g_v1" % (level, wid, m, leaf, tol)
+    path = os.path.join(CACHE_DIR, tag + ".npz")
+    ppath = os.path.join(CACHE_DIR, tag + "_problem.npz")
+    if cache and os.path.exists(path) and os.path.exists(ppath):
+        return load(path), load(ppath)
+    t0 = time.time()
+    v, f = sphere.perturbed_sphere(level, wid)
+    K, M = sphere.cotangent_fem(v, f)
+    lam, Phi = sphere.eigenpairs(K, M, m, workers=workers, log=log)
+    if log:
+        log(dict(eigenpairs_seconds=round(time.time() - t0, 1)))
+    n = len(v)
+    L = depth_for(n, leaf)
+    perm, xoff = mesh_fiedler_tree(K, M, L)
+    koff = frequency_tree(m, L)
+    Phi = np.ascontiguousarray(Phi)
+
+    def blocks(rows, cols):
+        return Phi[:, cols] if rows is None else Phi[np.ix_(rows, cols)]
+
+    fs = build_factors(blocks, n, m, perm, xoff, koff, L, tol, workers=workers, log=log)
+    problem = dict(v=v, f=f, M=M, lam=lam, Phi=Phi)
+    if cache:
+        os.makedirs(CACHE_DIR, exist_ok=True)
+        save(path, fs)
+        save(ppath, problem)
+    return fs, problem

@@ -25,6 +25,10 @@ WORKLOADS = {
 }
 
 
+# Perturbed sphere: icosphere level 6 (40962 vertices), r = 1 + 0.1 g, first 4096
+# generalized eigenvectors of the cotangent Laplacian, Fiedler tree, leaf 64.
+SPHERE = dict(wid=3, level=6, n=40962, m=4096, leaf=64, tol=1e-8, nrhs=256)
+
 # Many uneven instances in one call: 32 uniform-grid problems on the periodic
 # square, side drawn from SIDES, m = n / 4 modes, leaf 64, tol 1e-8, 1..128 RHS.
 BATCHED = dict(wid=4, count=32, sides=(32, 48, 64, 96, 128, 192, 256), leaf=64, tol=1e-8, max_nrhs=128)

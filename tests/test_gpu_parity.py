@@ -250,3 +250,22 @@ def test_iid_bf16_vs_dense(gpu, iid_medium, prec):
     e2 = _rel(_np(p.apply_t(_t(fv, torch.float32))), Phi.T @ fv)
     print("%s synthesis %.2e analysis %.2e" % (prec, e1, e2))
     assert e1 <= BF16_TOL[prec] and e2 <= BF16_TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def small_sphere():
+    return fio.sphere_factors(3, 3, 200, 16, 1e-8, workers=4, cache=False)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-7), ("f32", 1e-5), ("bf16x3", 1e-5), ("bf16x2", 1e-4)])
+def test_sphere_vs_dense(gpu, small_sphere, prec, tol):
+    """Perturbed icosphere (642 vertices, 200 eigenvectors, Fiedler tree) against the dense Phi."""
+    import torch
+    fs, prob = small_sphere
+    Phi = prob["Phi"]
+    c = np.random.default_rng(20).standard_normal((200, 256))
+    f = np.random.default_rng(21).standard_normal((Phi.shape[0], 256))
+    p = _plan(fs, prec, 256)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    assert _rel(_np(p.apply(_t(c, dt))), Phi @ c) <= tol
+    assert _rel(_np(p.apply_t(_t(f, dt))), Phi.T @ f) <= tol
