@@ -354,7 +354,7 @@ def main():
         "fp32_apply_alg_GBps": alg_bytes32 / (ms_fwd * 1e-3) / 1e9,
         "stored_factor_entries": F, "compression_vs_dense": n * m / F,
         "stage_launches_per_apply": launches,
-        "tile_cols": tuned,
+        "tile_shapes": tuned,
     }
     variants_out = {}
 

@@ -136,14 +136,15 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_
  * leaf stage), numbered in forward order; -1 for NULL. */
 int32_t bfmht_plan_num_stages(const bfmht_plan *plan);
 
-/* Tile width (right-hand-side columns per workgroup tile) of one stage of the
- * forward (transpose = 0) or transposed (transpose != 0) apply: 16, 32 or 64,
- * or 0 for the default (the smallest of 16, 32, 64 that covers nrhs).  Results
- * do not depend on it; it is the knob the autotuner sets.  EINVAL on a bad
- * stage or width. */
-bfmht_status bfmht_plan_set_tile_cols(bfmht_plan *plan, int32_t transpose, int32_t stage, int32_t cols);
-/* The value set for that stage (0 = default), -1 on a bad argument. */
-int32_t bfmht_plan_get_tile_cols(const bfmht_plan *plan, int32_t transpose, int32_t stage);
+/* Tile shape of one stage of the forward (transpose = 0) or transposed
+ * (transpose != 0) apply: `rows` output rows (64 or 128) by `cols`
+ * right-hand-side columns (16, 32 or 64, or 0 for the smallest of those that
+ * covers nrhs) per workgroup.  Default 64 x 0.  Results do not depend on it;
+ * it is the knob the autotuner sets.  EINVAL on a bad stage or shape. */
+bfmht_status bfmht_plan_set_tile(bfmht_plan *plan, int32_t transpose, int32_t stage, int32_t rows, int32_t cols);
+/* The shape set for that stage. */
+bfmht_status bfmht_plan_get_tile(const bfmht_plan *plan, int32_t transpose, int32_t stage, int32_t *rows,
+                                 int32_t *cols);
 
 /* Workspace bytes of a bfmht_apply_batched call with these plans and RHS
  * counts (count >= 0 plans, all of one precision); -1 on a bad argument. */

@@ -1,12 +1,14 @@
 """Tile-width autotuner for the butterfly apply.
 
-The tunable is the number of right-hand-side columns per workgroup tile of each
-stage (16, 32 or 64; `bfmht_plan_set_tile_cols`).  Narrower tiles read each
-factor row more than once but give a small stage more workgroups; which wins
-depends on the stage's shape and the RHS count, so it is measured.  The search
-is greedy over stages in order: every stage keeps the width that gives the
-fastest full apply, timed with HIP events on the current stream, the others
-held at their current choice.  Results are cached in a JSON file keyed by the
+The tunable is the workgroup tile shape of each stage (`bfmht_plan_set_tile`):
+64 or 128 output rows by 16, 32 or 64 right-hand-side columns.  Narrower tiles
+read each factor row more than once but give a small stage more workgroups;
+taller tiles halve the LDS traffic and right-hand-side re-reads per flop but
+waste more rows on ragged blocks and leave fewer workgroups.  Which wins
+depends on the stage's shape, the precision and the RHS count, so it is
+measured.  The search is greedy over stages in order: every stage keeps the
+shape that gives the fastest full apply, timed with HIP events on the current
+stream, the others held at their current choice.  Results are cached in a JSON file keyed by the
 plan's shape (sizes, ranks, precision) and the RHS count.
 """
 import hashlib
@@ -18,6 +20,8 @@ import numpy as np
 from . import bfmht as B
 
 WIDTHS = (16, 32, 64)
+HEIGHTS = (64, 128)
+SHAPES = [(r, c) for r in HEIGHTS for c in WIDTHS]
 CACHE = os.environ.get("BFMHT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "bfmht", "tune.json"))
 
 
@@ -60,8 +64,8 @@ def _time(fn, reps, torch):
 
 def apply_config(plan, config):
     for d, key in ((0, "fwd"), (1, "bwd")):
-        for k, w in enumerate(config.get(key, [])):
-            B.bfmht_plan_set_tile_cols(plan.handle, d, k, w)
+        for k, (r, c) in enumerate(config.get(key, [])):
+            B.bfmht_plan_set_tile(plan.handle, d, k, r, c)
 
 
 def tune_plan(plan, fs, nrhs, reps=10, cache_path=CACHE, use_cache=True, log=None):
@@ -79,21 +83,23 @@ def tune_plan(plan, fs, nrhs, reps=10, cache_path=CACHE, use_cache=True, log=Non
     S = B.bfmht_plan_num_stages(plan.handle)
     config = {}
     for d, key_d, fn in ((0, "fwd", lambda: plan.apply(x, out=out_f)), (1, "bwd", lambda: plan.apply_t(y, out=out_b))):
-        choice = [0] * S
+        choice = [(64, 0)] * S
         for k in range(S):
-            B.bfmht_plan_set_tile_cols(plan.handle, d, k, 0)
+            B.bfmht_plan_set_tile(plan.handle, d, k, 64, 0)
         base = _time(fn, reps, torch)
         for k in range(S):
-            best_w, best_t = choice[k], base
-            for w in WIDTHS:
-                B.bfmht_plan_set_tile_cols(plan.handle, d, k, w)
+            best, best_t = choice[k], base
+            for r, c in SHAPES:
+                if c > 16 and nrhs <= c // 2:
+                    continue  # wider than twice the RHS count only adds idle columns
+                B.bfmht_plan_set_tile(plan.handle, d, k, r, c)
                 t = _time(fn, reps, torch)
                 if t < best_t * 0.995:
-                    best_w, best_t = w, t
-            choice[k] = best_w
-            B.bfmht_plan_set_tile_cols(plan.handle, d, k, best_w)
+                    best, best_t = (r, c), t
+            choice[k] = best
+            B.bfmht_plan_set_tile(plan.handle, d, k, *best)
             base = min(base, best_t)
-        config[key_d] = choice
+        config[key_d] = [list(c) for c in choice]
         config[key_d + "_ms"] = base
         if log:
             log("autotune %s: %s -> %.3f ms" % (key_d, choice, base))
@@ -105,16 +111,16 @@ def tune_plan(plan, fs, nrhs, reps=10, cache_path=CACHE, use_cache=True, log=Non
 
 
 def tune_batch(batch, inputs, transpose=False, reps=5, log=None):
-    """Choose one uniform tile width per distinct plan of a batch (0 = by nrhs)
-    by greedy search over plans, timing the whole batched apply."""
+    """Choose one uniform tile shape per distinct plan of a batch by greedy
+    search over plans, timing the whole batched apply."""
     torch = batch.torch
     outs = [torch.empty(((p.m if transpose else p.n), int(x.shape[1])), dtype=p.dtype, device=batch.device)
             for p, x in zip(batch.plans, inputs)]
     d = 1 if transpose else 0
 
-    def set_all(p, w):
+    def set_all(p, shape):
         for k in range(B.bfmht_plan_num_stages(p.handle)):
-            B.bfmht_plan_set_tile_cols(p.handle, d, k, w)
+            B.bfmht_plan_set_tile(p.handle, d, k, *shape)
 
     def fn():
         batch.launch(inputs, outs, transpose)
@@ -126,21 +132,21 @@ def tune_batch(batch, inputs, transpose=False, reps=5, log=None):
             widest[id(p)] = 0
         widest[id(p)] = max(widest[id(p)], int(x.shape[1]))
     for p in distinct:
-        set_all(p, 0)
+        set_all(p, (64, 0))
     base = _time(fn, reps, torch)
     choice = []
     for p in distinct:
-        best_w, best_t = 0, base
-        for w in WIDTHS:
-            if w > 16 and widest[id(p)] <= w // 2:
+        best, best_t = (64, 0), base
+        for r, c in SHAPES:
+            if c > 16 and widest[id(p)] <= c // 2:
                 continue  # wider than twice the largest RHS count only adds idle columns
-            set_all(p, w)
+            set_all(p, (r, c))
             t = _time(fn, reps, torch)
             if t < best_t * 0.995:
-                best_w, best_t = w, t
-        set_all(p, best_w)
-        choice.append(best_w)
+                best, best_t = (r, c), t
+        set_all(p, best)
+        choice.append(best)
         base = min(base, best_t)
     if log:
-        log("autotune batch (%s): widths %s -> %.3f ms" % ("transpose" if transpose else "forward", choice, base))
+        log("autotune batch (%s): shapes %s -> %.3f ms" % ("transpose" if transpose else "forward", choice, base))
     return choice, base

@@ -39,7 +39,7 @@ class bfmht_factors_host(ctypes.Structure):
 EXPORTED = [
     "bfmht_plan_create", "bfmht_plan_device_bytes", "bfmht_workspace_bytes", "bfmht_plan_upload",
     "bfmht_apply", "bfmht_apply_transpose", "bfmht_plan_destroy", "bfmht_last_error", "bfmht_version",
-    "bfmht_plan_num_stages", "bfmht_plan_set_tile_cols", "bfmht_plan_get_tile_cols",
+    "bfmht_plan_num_stages", "bfmht_plan_set_tile", "bfmht_plan_get_tile",
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
 ]
 
@@ -69,10 +69,10 @@ def load_library(path=LIB_PATH):
     lib.bfmht_version.restype = ctypes.c_char_p
     lib.bfmht_plan_num_stages.argtypes = [vp]
     lib.bfmht_plan_num_stages.restype = i32
-    lib.bfmht_plan_set_tile_cols.argtypes = [vp, i32, i32, i32]
-    lib.bfmht_plan_set_tile_cols.restype = ctypes.c_int
-    lib.bfmht_plan_get_tile_cols.argtypes = [vp, i32, i32]
-    lib.bfmht_plan_get_tile_cols.restype = i32
+    lib.bfmht_plan_set_tile.argtypes = [vp, i32, i32, i32, i32]
+    lib.bfmht_plan_set_tile.restype = ctypes.c_int
+    lib.bfmht_plan_get_tile.argtypes = [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.bfmht_plan_get_tile.restype = ctypes.c_int
     pp = ctypes.POINTER(vp)
     lib.bfmht_batched_workspace_bytes.argtypes = [pp, i32, ctypes.POINTER(i32)]
     lib.bfmht_batched_workspace_bytes.restype = i64
@@ -156,12 +156,15 @@ def bfmht_plan_num_stages(plan):
     return lib.bfmht_plan_num_stages(plan)
 
 
-def bfmht_plan_set_tile_cols(plan, transpose, stage, cols):
-    _check(lib.bfmht_plan_set_tile_cols(plan, int(transpose), int(stage), int(cols)), "bfmht_plan_set_tile_cols")
+def bfmht_plan_set_tile(plan, transpose, stage, rows, cols):
+    _check(lib.bfmht_plan_set_tile(plan, int(transpose), int(stage), int(rows), int(cols)), "bfmht_plan_set_tile")
 
 
-def bfmht_plan_get_tile_cols(plan, transpose, stage):
-    return lib.bfmht_plan_get_tile_cols(plan, int(transpose), int(stage))
+def bfmht_plan_get_tile(plan, transpose, stage):
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.bfmht_plan_get_tile(plan, int(transpose), int(stage), ctypes.byref(r), ctypes.byref(c)),
+           "bfmht_plan_get_tile")
+    return r.value, c.value
 
 
 def _arr(ctype, vals):

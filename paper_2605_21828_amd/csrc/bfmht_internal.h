@@ -72,13 +72,16 @@ struct StageArgs {
   int32_t nrhs;
 };
 
-// Output rows per workgroup tile; the plan builds its tile lists for this height.
+// Output rows per workgroup tile at one 16-row block per wave; tiles of twice
+// that height (two blocks per wave) are the other shape.  The plan builds tile
+// lists for both heights.
 constexpr int kTileRows = 64;
 
-// Launch one stage with tiles of bn RHS columns (16, 32 or 64).  Returns 0 or a
-// hipError_t value.
-int launch_fwd_stage(int prec, const StageArgs &a, int bn, void *stream);
-int launch_bwd_stage(int prec, const StageArgs &a, int bn, void *stream);
+// Launch one stage with tiles of `rows` (64 or 128) output rows and `cols`
+// (16, 32 or 64) RHS columns; a.tiles must be the list built for that height.
+// Returns 0 or a hipError_t value.
+int launch_fwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
+int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
 
 // One stage of one instance inside a batched launch.
 struct Segment {
@@ -86,12 +89,22 @@ struct Segment {
   int32_t fwd;     // 1: forward stage, 0: transposed stage
   int32_t bn;      // RHS columns per tile (16, 32, 64)
   int32_t ny;      // column tiles
-  int32_t pad;
+  int32_t fm;      // 16-row blocks per wave (tile height 64 fm)
   int64_t item0;   // first work item (block index) of this segment in its launch
   int64_t nitems;  // a.ntiles * ny
 };
 
-// One launch over `items` work items of `nseg` segments (all of one stage position).
-int launch_batched_stage(int prec, const Segment *segs_dev, int32_t nseg, int64_t items, void *stream);
+// Segments travel to the batched kernel as launch arguments (no device table),
+// at most kSegsPerLaunch per launch.
+constexpr int kSegsPerLaunch = 24;
+struct SegPack {
+  int32_t nseg;
+  int32_t pad;
+  Segment s[kSegsPerLaunch];
+};
+static_assert(sizeof(SegPack) <= 4096, "launch arguments are limited to 4 KB");
+
+// One launch over `items` work items of the pack's segments (item0 relative to the pack).
+int launch_batched_stage(int prec, const SegPack &pack, int64_t items, void *stream);
 
 }  // namespace bfmht

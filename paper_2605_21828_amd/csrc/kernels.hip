@@ -5,18 +5,19 @@
 // are each applied once per vector, which is why storage and apply cost
 // coincide, Sec. 7.2).
 //
-// Work split.  A workgroup of 4 waves computes a 64-row x BN-column output tile
-// of one job; each wave owns 16 rows and all BN columns, so every factor element
-// is used by exactly one wave.  Factor rows therefore go straight from HBM into
-// MFMA operand registers (no LDS round trip): per reduction chunk a lane loads
-// 32 contiguous bytes of its row, and the four lane groups together cover one
-// 128-byte line per row.  The reduction index is permuted inside a chunk (lane
-// group g and step t take k = KL*g + t), which is legal because both operands
-// use the same permutation.  The right-hand-side chunk (KC rows x BN columns) is
-// shared by the 4 waves and staged through LDS, transposed so that each lane
-// reads its KL consecutive k values with 16-byte LDS reads.  LDS is double
-// buffered: the loads of chunk c+1 are in flight while chunk c runs on the
-// matrix cores, with one barrier per chunk.
+// Work split.  A workgroup of 4 waves computes a (64 FM)-row x BN-column output
+// tile of one job; each wave owns FM blocks of 16 rows and all BN columns, so
+// every factor element is used by exactly one wave.  Factor rows therefore go
+// straight from HBM into MFMA operand registers (no LDS round trip): per
+// reduction chunk a lane loads 32 contiguous bytes of each of its rows, and the
+// four lane groups together cover one 128-byte line per row.  The reduction
+// index is permuted inside a chunk (lane group g and step t take k = KL g + t),
+// which is legal because both operands use the same permutation.  The
+// right-hand-side chunk (KC rows x BN columns) is shared by the 4 waves and
+// staged through LDS, transposed so that each lane reads its KL consecutive k
+// values with 16-byte LDS reads; with FM = 2 each of those reads feeds two
+// MFMA row blocks.  LDS is double buffered: the loads of chunk c+1 are in
+// flight while chunk c runs on the matrix cores, with one barrier per chunk.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -53,7 +54,7 @@ __device__ __forceinline__ int acc_row(double, int lane, int i) { return 4 * i +
 
 constexpr int kWaves = 4;
 constexpr int kNT = 64 * kWaves;
-static_assert(kTileRows == 16 * kWaves, "one 16-row MFMA block per wave");
+static_assert(kTileRows == 16 * kWaves, "one 16-row MFMA block per wave at FM = 1");
 
 // Copy N elements (N * sizeof(T) a multiple of 8 bytes) with 16- or 8-byte accesses.
 template <typename T, int N>
@@ -68,6 +69,26 @@ __device__ __forceinline__ void copy_vec(T *dst, const T *src) {
     for (int i = 0; i < bytes / 8; ++i) reinterpret_cast<uint2 *>(dst)[i] = reinterpret_cast<const uint2 *>(src)[i];
   }
 }
+
+// Destination row of output row r of a forward job (through the stage row map if any).
+__device__ __forceinline__ int64_t out_row(const StageArgs &a, int32_t base, int r) {
+  return a.rowmap ? (int64_t)a.rowmap[base + r] : (int64_t)(base + r);
+}
+
+// Identity block: copy rows [m0, m0 + rows) of the job.
+template <typename T, int BN>
+__device__ __forceinline__ void copy_tile(const StageArgs &a, const FwdJob &J, int m0, int rows, int n0) {
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  for (int e = threadIdx.x; e < rows * BN; e += kNT) {
+    const int r = e / BN, c = e % BN;
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < J.M && gc < a.nrhs) dst[out_row(a, J.out_row, gr) * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 and FP64: 16x16x4 MFMA.
 
 template <typename T, int BN>
 struct Tiling {
@@ -112,7 +133,8 @@ __device__ __forceinline__ void store_x(T *Xs, const T *xr, int tid) {
   for (int i = 0; i < Tl::XR; ++i) Xs[(c + i) * Tl::XS + k] = xr[i];
 }
 
-// Load this lane's KL reduction values of factor row `wrow` for the chunk at k0.
+// This lane's KL reduction values of factor row `wrow` for the chunk at k0.
+// Row strides are multiples of 8 >= KL, so a lane's values lie in one row.
 template <typename T, int BN>
 __device__ __forceinline__ void load_w(T *wr, const T *wrow, int ldw, int k0, int lg) {
   typedef Tiling<T, BN> Tl;
@@ -125,156 +147,149 @@ __device__ __forceinline__ void load_w(T *wr, const T *wrow, int ldw, int k0, in
   }
 }
 
-// acc += W_chunk (this wave's 16 rows) * X_chunk (all BN columns).
-template <typename T, int BN>
-__device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t *acc, const T *wr, const T *Xs, int lrow, int lg) {
+// acc += W_chunk (this wave's FM x 16 rows) * X_chunk (all BN columns).
+template <typename T, int BN, int FM>
+__device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16], const T (*wr)[Cfg<T>::KC / 4],
+                                          const T *Xs, int lrow, int lg) {
   typedef Tiling<T, BN> Tl;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
     T b[Tl::KL];
     copy_vec<T, Tl::KL>(b, &Xs[(fn * 16 + lrow) * Tl::XS + Tl::KL * lg]);
 #pragma unroll
-    for (int t = 0; t < Tl::KL; ++t) acc[fn] = mfma16x16x4(wr[t], b[t], acc[fn]);
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int t = 0; t < Tl::KL; ++t) acc[fm][fn] = mfma16x16x4(wr[fm][t], b[t], acc[fm][fn]);
   }
 }
 
 // Reduction over one factor block: acc += W(rows of this wave) * src rows.
 // W is row-major with stride ldw; the reduction runs over nk source rows read
 // through the optional row map starting at `base`.
-template <typename T, int BN>
-__device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t *acc, const T *wrow, int ldw, int nk,
-                                           const StageArgs &a, const int32_t *rowmap, int32_t base, int n0, T *Xs,
-                                           int tid, int lrow, int lg) {
+template <typename T, int BN, int FM>
+__device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int ldw,
+                                           int nk, const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
+                                           T *Xs, int tid, int lrow, int lg) {
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
-  T wA[Tl::KL], wB[Tl::KL], xB[Tl::XR];
-  load_w<T, BN>(wA, wrow, ldw, 0, lg);
+  T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(wA[fm], wrow[fm], ldw, 0, lg);
   load_x<T, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
   store_x<T, BN>(Xs, xB, tid);
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
     const bool more = c + 1 < nchunk;
     if (more) {
-      load_w<T, BN>(wB, wrow, ldw, (c + 1) * Tl::KC, lg);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
       load_x<T, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
     }
-    mma_chunk<T, BN>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    mma_chunk<T, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
     if (more) {
       store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
 #pragma unroll
-      for (int i = 0; i < Tl::KL; ++i) wA[i] = wB[i];
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int i = 0; i < Tl::KL; ++i) wA[fm][i] = wB[fm][i];
     }
     __syncthreads();
   }
 }
 
-// Forward stage: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
-template <typename T, int BN>
+// Forward stage tile: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
+template <typename T, int BN, int FM>
 __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
   const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
-  const T *src = static_cast<const T *>(a.src);
-  T *dst = static_cast<T *>(a.dst);
-  const int tid = threadIdx.x;
-
   if (J.w_off < 0) {  // identity block: copy its rows
-    for (int e = tid; e < kTileRows * BN; e += kNT) {
-      const int r = e / BN, c = e % BN;
-      const int gr = tile.m0 + r, gc = n0 + c;
-      if (gr < J.M && gc < a.nrhs) {
-        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
-        dst[drow * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
-      }
-    }
+    copy_tile<T, BN>(a, J, tile.m0, kTileRows * FM, n0);
     return;
   }
-
+  const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
-  const int row = tile.m0 + wave * 16 + lrow;  // factor row this lane streams
-  const T *wrow = static_cast<const T *>(a.pool) + J.w_off + (int64_t)min(row, J.M - 1) * J.ldw;
-  typename Cfg<T>::acc_t acc[Tl::FN];
+  const int rbase = tile.m0 + wave * 16 * FM;
+  const T *wrow[FM];
 #pragma unroll
-  for (int i = 0; i < Tl::FN; ++i) acc[i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  gemm_block<T, BN>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
-
+  for (int fm = 0; fm < FM; ++fm)
+    wrow[fm] = static_cast<const T *>(a.pool) + J.w_off + (int64_t)min(rbase + fm * 16 + lrow, J.M - 1) * J.ldw;
+  typename Cfg<T>::acc_t acc[FM][Tl::FN];
 #pragma unroll
-  for (int fn = 0; fn < Tl::FN; ++fn)
+  for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gr = tile.m0 + wave * 16 + acc_row(T(0), lane, i);
-      const int gc = n0 + fn * 16 + lrow;
-      if (gr < J.M && gc < a.nrhs) {
-        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
-        dst[drow * a.ldd + gc] = acc[fn][i];
+    for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
+  gemm_block<T, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+  T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = rbase + fm * 16 + acc_row(T(0), lane, i);
+        const int gc = n0 + fn * 16 + lrow;
+        if (gr < J.M && gc < a.nrhs) dst[out_row(a, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
       }
-    }
 }
 
-// Transposed stage: dst[out_row .. out_row+K) = sum over consumers of W_c^T g_c,
-// identity consumers adding their gradient rows directly.
-template <typename T, int BN>
+// Transposed stage tile: dst[out_row .. out_row+K) = sum over consumers of
+// W_c^T g_c, identity consumers adding their gradient rows directly.
+template <typename T, int BN, int FM>
 __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
   const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
-  const T *src = static_cast<const T *>(a.src);
-  T *dst = static_cast<T *>(a.dst);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
-  const int row = min(tile.m0 + wave * 16 + lrow, J.K - 1);  // row of W^T (column of W)
-  typename Cfg<T>::acc_t acc[Tl::FN];
+  const int rbase = tile.m0 + wave * 16 * FM;
+  typename Cfg<T>::acc_t acc[FM][Tl::FN];
 #pragma unroll
-  for (int i = 0; i < Tl::FN; ++i) acc[i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
   for (int ci = 0; ci < J.nc; ++ci) {
     const Cons C = J.c[ci];
     if (C.wt_off < 0) continue;
-    const T *wrow = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)row * C.ldwt;
-    gemm_block<T, BN>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
+    const T *wrow[FM];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
+      wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
+    gemm_block<T, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
   }
-
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
 #pragma unroll
-  for (int fn = 0; fn < Tl::FN; ++fn)
+  for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gr = tile.m0 + wave * 16 + acc_row(T(0), lane, i);
-      const int gc = n0 + fn * 16 + lrow;
-      if (gr < J.K && gc < a.nrhs) {
-        T v = acc[fn][i];
-        for (int ci = 0; ci < J.nc; ++ci)
-          if (J.c[ci].wt_off < 0) {
-            const int32_t b = J.c[ci].g_row;
-            const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
-            v += src[srow * a.lds + gc];
-          }
-        dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+    for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = rbase + fm * 16 + acc_row(T(0), lane, i);
+        const int gc = n0 + fn * 16 + lrow;
+        if (gr < J.K && gc < a.nrhs) {
+          T v = acc[fm][fn][i];
+          for (int ci = 0; ci < J.nc; ++ci)
+            if (J.c[ci].wt_off < 0) {
+              const int32_t b = J.c[ci].g_row;
+              const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
+              v += src[srow * a.lds + gc];
+            }
+          dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+        }
       }
-    }
-}
-
-template <typename T, int BN>
-__global__ __launch_bounds__(kNT) void fwd_stage_kernel(StageArgs a) {
-  __shared__ __attribute__((aligned(16))) T Xs[2 * Tiling<T, BN>::XBUF];
-  fwd_tile<T, BN>(a, blockIdx.x, blockIdx.y, Xs);
-}
-
-template <typename T, int BN>
-__global__ __launch_bounds__(kNT) void bwd_stage_kernel(StageArgs a) {
-  __shared__ __attribute__((aligned(16))) T Xs[2 * Tiling<T, BN>::XBUF];
-  bwd_tile<T, BN>(a, blockIdx.x, blockIdx.y, Xs);
 }
 
 // ---------------------------------------------------------------------------
 // BF16 split products.  A factor value w is stored as 2 or 3 bfloat16 terms
 // (hi = bf16(w), lo = bf16(w - hi), lo2 = bf16(w - hi - lo)); right-hand-side
 // values are split the same way when a chunk is staged into LDS (once per
-// workgroup).  Products of terms whose indices sum to at most NT-1 are
+// workgroup).  Products of terms whose indices sum to at most NTERM-1 are
 // accumulated in FP32 by v_mfma_f32_16x16x32_bf16: hi*hi + hi*lo + lo*hi for
 // two terms, plus hi*lo2 + lo*lo + lo2*hi for three.  Only the output layout of
 // the instruction matters here: both operands use the same (lane group, element)
@@ -359,8 +374,7 @@ __device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int ti
 // term).  Row strides are multiples of 8 values, so each 8-value half is either
 // entirely inside the row or entirely past its end.
 template <int NTERM, int BN>
-__device__ __forceinline__ void load_w_bf(uint4 (&wr)[NTERM][2], const uint16_t *const (&wrow)[3], int ldw, int k0,
-                                          int lg) {
+__device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const *wrow, int ldw, int k0, int lg) {
   typedef TilingB<NTERM, BN> Tl;
   const int k = k0 + Tl::KL * lg;
 #pragma unroll
@@ -370,9 +384,9 @@ __device__ __forceinline__ void load_w_bf(uint4 (&wr)[NTERM][2], const uint16_t 
       wr[t][h] = k + 8 * h < ldw ? *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h) : make_uint4(0, 0, 0, 0);
 }
 
-template <int NTERM, int BN>
-__device__ __forceinline__ void mma_chunk_bf(v4f *acc, const uint4 (&wr)[NTERM][2], const uint16_t *Xs, int lrow,
-                                             int lg) {
+template <int NTERM, int BN, int FM>
+__device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*wr)[NTERM][2], const uint16_t *Xs,
+                                             int lrow, int lg) {
   typedef TilingB<NTERM, BN> Tl;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
@@ -382,284 +396,266 @@ __device__ __forceinline__ void mma_chunk_bf(v4f *acc, const uint4 (&wr)[NTERM][
       uint4 b[NTERM];
 #pragma unroll
       for (int t = 0; t < NTERM; ++t) b[t] = *reinterpret_cast<const uint4 *>(Xs + t * 2 * Tl::XBUF + off + 8 * h);
-      // smallest products first
-      if constexpr (NTERM == 3) {
-        acc[fn] = mfma_bf16(wr[2][h], b[0], acc[fn]);
-        acc[fn] = mfma_bf16(wr[1][h], b[1], acc[fn]);
-        acc[fn] = mfma_bf16(wr[0][h], b[2], acc[fn]);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        // smallest products first
+        if constexpr (NTERM == 3) {
+          acc[fm][fn] = mfma_bf16(wr[fm][2][h], b[0], acc[fm][fn]);
+          acc[fm][fn] = mfma_bf16(wr[fm][1][h], b[1], acc[fm][fn]);
+          acc[fm][fn] = mfma_bf16(wr[fm][0][h], b[2], acc[fm][fn]);
+        }
+        acc[fm][fn] = mfma_bf16(wr[fm][1][h], b[0], acc[fm][fn]);
+        acc[fm][fn] = mfma_bf16(wr[fm][0][h], b[1], acc[fm][fn]);
+        acc[fm][fn] = mfma_bf16(wr[fm][0][h], b[0], acc[fm][fn]);
       }
-      acc[fn] = mfma_bf16(wr[1][h], b[0], acc[fn]);
-      acc[fn] = mfma_bf16(wr[0][h], b[1], acc[fn]);
-      acc[fn] = mfma_bf16(wr[0][h], b[0], acc[fn]);
     }
   }
 }
 
 // Reduction over one factor block with split terms.  Xs holds 2 buffers per
-// term: term t buffer j at Xs + (2 t + j) * XBUF.
-template <int NTERM, int BN>
-__device__ __forceinline__ void gemm_block_bf(v4f *acc, const uint16_t *const (&wrow)[3], int ldw, int nk,
+// term: term t buffer j at Xs + (2 t + j) * XBUF.  wrow[fm][t]: term t of row fm.
+template <int NTERM, int BN, int FM>
+__device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int ldw, int nk,
                                               const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
                                               uint16_t *Xs, int tid, int lrow, int lg) {
   typedef TilingB<NTERM, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
-  uint4 wA[NTERM][2], wB[NTERM][2];
+  uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
-  load_w_bf<NTERM, BN>(wA, wrow, ldw, 0, lg);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(wA[fm], wrow[fm], ldw, 0, lg);
   load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
   store_x_bf<NTERM, BN>(Xs, xB, tid);
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
     const bool more = c + 1 < nchunk;
     if (more) {
-      load_w_bf<NTERM, BN>(wB, wrow, ldw, (c + 1) * Tl::KC, lg);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
       load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
     }
-    mma_chunk_bf<NTERM, BN>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
     if (more) {
       store_x_bf<NTERM, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t) {
-        wA[t][0] = wB[t][0];
-        wA[t][1] = wB[t][1];
-      }
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int t = 0; t < NTERM; ++t) {
+          wA[fm][t][0] = wB[fm][t][0];
+          wA[fm][t][1] = wB[fm][t][1];
+        }
     }
     __syncthreads();
   }
 }
 
-template <int NTERM, int BN>
+template <int NTERM, int BN, int FM>
 __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
   const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
-  const float *src = static_cast<const float *>(a.src);
-  float *dst = static_cast<float *>(a.dst);
-  const int tid = threadIdx.x;
-
   if (J.w_off < 0) {  // identity block: copy its rows
-    for (int e = tid; e < kTileRows * BN; e += kNT) {
-      const int r = e / BN, c = e % BN;
-      const int gr = tile.m0 + r, gc = n0 + c;
-      if (gr < J.M && gc < a.nrhs) {
-        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
-        dst[drow * a.ldd + gc] = src[(int64_t)(J.in_row + gr) * a.lds + gc];
-      }
-    }
+    copy_tile<float, BN>(a, J, tile.m0, kTileRows * FM, n0);
     return;
   }
+  const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
-  const int row = tile.m0 + wave * 16 + lrow;
-  const int64_t roff = J.w_off + (int64_t)min(row, J.M - 1) * J.ldw;
-  const uint16_t *const wrow[3] = {static_cast<const uint16_t *>(a.pool) + roff,
-                                   static_cast<const uint16_t *>(a.pool_lo) + roff,
-                                   NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr};
-  v4f acc[Tl::FN];
+  const int rbase = tile.m0 + wave * 16 * FM;
+  const uint16_t *wrow[FM][3];
 #pragma unroll
-  for (int i = 0; i < Tl::FN; ++i) acc[i] = v4f{0, 0, 0, 0};
-  gemm_block_bf<NTERM, BN>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+  for (int fm = 0; fm < FM; ++fm) {
+    const int64_t roff = J.w_off + (int64_t)min(rbase + fm * 16 + lrow, J.M - 1) * J.ldw;
+    wrow[fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
+    wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
+    wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
+  }
+  v4f acc[FM][Tl::FN];
 #pragma unroll
-  for (int fn = 0; fn < Tl::FN; ++fn)
+  for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gr = tile.m0 + wave * 16 + acc_row(0.f, lane, i);
-      const int gc = n0 + fn * 16 + lrow;
-      if (gr < J.M && gc < a.nrhs) {
-        const int64_t drow = a.rowmap ? (int64_t)a.rowmap[J.out_row + gr] : (int64_t)(J.out_row + gr);
-        dst[drow * a.ldd + gc] = acc[fn][i];
+    for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
+  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+  float *dst = static_cast<float *>(a.dst);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = rbase + fm * 16 + acc_row(0.f, lane, i);
+        const int gc = n0 + fn * 16 + lrow;
+        if (gr < J.M && gc < a.nrhs) dst[out_row(a, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
       }
-    }
 }
 
-template <int NTERM, int BN>
+template <int NTERM, int BN, int FM>
 __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
   const Tile tile = a.tiles[tix];
   if (tile.job < 0) return;  // padding tile of a short XCD bin
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
-  const float *src = static_cast<const float *>(a.src);
-  float *dst = static_cast<float *>(a.dst);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
-  const int row = min(tile.m0 + wave * 16 + lrow, J.K - 1);
-  v4f acc[Tl::FN];
+  const int rbase = tile.m0 + wave * 16 * FM;
+  v4f acc[FM][Tl::FN];
 #pragma unroll
-  for (int i = 0; i < Tl::FN; ++i) acc[i] = v4f{0, 0, 0, 0};
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
   for (int ci = 0; ci < J.nc; ++ci) {
     const Cons C = J.c[ci];
     if (C.wt_off < 0) continue;
-    const int64_t roff = C.wt_off + (int64_t)row * C.ldwt;
-    const uint16_t *const wrow[3] = {static_cast<const uint16_t *>(a.pool) + roff,
-                                     static_cast<const uint16_t *>(a.pool_lo) + roff,
-                                     NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr};
-    gemm_block_bf<NTERM, BN>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
-  }
+    const uint16_t *wrow[FM][3];
 #pragma unroll
-  for (int fn = 0; fn < Tl::FN; ++fn)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gr = tile.m0 + wave * 16 + acc_row(0.f, lane, i);
-      const int gc = n0 + fn * 16 + lrow;
-      if (gr < J.K && gc < a.nrhs) {
-        float v = acc[fn][i];
-        for (int ci = 0; ci < J.nc; ++ci)
-          if (J.c[ci].wt_off < 0) {
-            const int32_t b = J.c[ci].g_row;
-            const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
-            v += src[srow * a.lds + gc];
-          }
-        dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
-      }
+    for (int fm = 0; fm < FM; ++fm) {
+      const int64_t roff = C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
+      wrow[fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
+      wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
+      wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
+    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
+  }
+  const float *src = static_cast<const float *>(a.src);
+  float *dst = static_cast<float *>(a.dst);
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < Tl::FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gr = rbase + fm * 16 + acc_row(0.f, lane, i);
+        const int gc = n0 + fn * 16 + lrow;
+        if (gr < J.K && gc < a.nrhs) {
+          float v = acc[fm][fn][i];
+          for (int ci = 0; ci < J.nc; ++ci)
+            if (J.c[ci].wt_off < 0) {
+              const int32_t b = J.c[ci].g_row;
+              const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
+              v += src[srow * a.lds + gc];
+            }
+          dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+        }
+      }
 }
 
-template <int NTERM, int BN>
-__global__ __launch_bounds__(kNT) void fwd_stage_bf16_kernel(StageArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * TilingB<NTERM, BN>::XBUF];
-  fwd_tile_bf<NTERM, BN>(a, blockIdx.x, blockIdx.y, Xs);
-}
+// ---------------------------------------------------------------------------
+// One tile of any precision, tile width and height.
 
-template <int NTERM, int BN>
-__global__ __launch_bounds__(kNT) void bwd_stage_bf16_kernel(StageArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2 * NTERM * TilingB<NTERM, BN>::XBUF];
-  bwd_tile_bf<NTERM, BN>(a, blockIdx.x, blockIdx.y, Xs);
-}
+template <int P, int BN> struct LdsBytes;
+template <int BN> struct LdsBytes<P_F64, BN> { static constexpr int bytes = 2 * Tiling<double, BN>::XBUF * 8; };
+template <int BN> struct LdsBytes<P_F32, BN> { static constexpr int bytes = 2 * Tiling<float, BN>::XBUF * 4; };
+template <int BN> struct LdsBytes<P_BF16X2, BN> { static constexpr int bytes = 2 * 2 * TilingB<2, BN>::XBUF * 2; };
+template <int BN> struct LdsBytes<P_BF16X3, BN> { static constexpr int bytes = 2 * 3 * TilingB<3, BN>::XBUF * 2; };
 
-template <int NTERM, int BN>
-static int launch_bf_t(bool fwd, const StageArgs &a, void *stream) {
-  if (a.ntiles == 0) return 0;
-  dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
-  if (fwd)
-    hipLaunchKernelGGL((fwd_stage_bf16_kernel<NTERM, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
-  else
-    hipLaunchKernelGGL((bwd_stage_bf16_kernel<NTERM, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
-}
-
-
-template <typename T, int BN>
-static int launch_t(bool fwd, const StageArgs &a, void *stream) {
-  if (a.ntiles == 0) return 0;
-  dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
-  if (fwd)
-    hipLaunchKernelGGL((fwd_stage_kernel<T, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
-  else
-    hipLaunchKernelGGL((bwd_stage_kernel<T, BN>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
-}
-
-// Tile width for a stage: an explicit 16/32/64, or the smallest that covers nrhs.
-static int pick_bn(int bn, int nrhs) {
-  if (bn == 16 || bn == 32 || bn == 64) return bn;
-  return nrhs <= 16 ? 16 : (nrhs <= 32 ? 32 : 64);
-}
-
-template <typename T>
-static int launch_bn(bool fwd, const StageArgs &a, int bn, void *stream) {
-  switch (pick_bn(bn, a.nrhs)) {
-    case 16: return launch_t<T, 16>(fwd, a, stream);
-    case 32: return launch_t<T, 32>(fwd, a, stream);
-    default: return launch_t<T, 64>(fwd, a, stream);
+template <int P, bool FWD, int BN, int FM>
+__device__ __forceinline__ void run_tile(const StageArgs &a, int tix, int ny, void *lds) {
+  if constexpr (P == P_F64 || P == P_F32) {
+    typedef typename std::conditional<P == P_F64, double, float>::type T;
+    if constexpr (FWD) fwd_tile<T, BN, FM>(a, tix, ny, static_cast<T *>(lds));
+    else bwd_tile<T, BN, FM>(a, tix, ny, static_cast<T *>(lds));
+  } else {
+    constexpr int NTERM = P == P_BF16X2 ? 2 : 3;
+    if constexpr (FWD) fwd_tile_bf<NTERM, BN, FM>(a, tix, ny, static_cast<uint16_t *>(lds));
+    else bwd_tile_bf<NTERM, BN, FM>(a, tix, ny, static_cast<uint16_t *>(lds));
   }
 }
 
-template <int NTERM>
-static int launch_bf(bool fwd, const StageArgs &a, int bn, void *stream) {
-  switch (pick_bn(bn, a.nrhs)) {
-    case 16: return launch_bf_t<NTERM, 16>(fwd, a, stream);
-    case 32: return launch_bf_t<NTERM, 32>(fwd, a, stream);
-    default: return launch_bf_t<NTERM, 64>(fwd, a, stream);
-  }
+template <int P, bool FWD, int BN, int FM>
+__global__ __launch_bounds__(kNT) void stage_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, BN>::bytes];
+  run_tile<P, FWD, BN, FM>(a, blockIdx.x, blockIdx.y, lds);
 }
 
-static int launch(bool fwd, int prec, const StageArgs &a, int bn, void *stream) {
-  switch (prec) {
-    case P_F64: return launch_bn<double>(fwd, a, bn, stream);
-    case P_F32: return launch_bn<float>(fwd, a, bn, stream);
-    case P_BF16X2: return launch_bf<2>(fwd, a, bn, stream);
-    case P_BF16X3: return launch_bf<3>(fwd, a, bn, stream);
+template <int P, bool FWD, int BN, int FM>
+static int launch_one(const StageArgs &a, void *stream) {
+  if (a.ntiles == 0) return 0;
+  dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
+  hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+template <int P, bool FWD>
+static int launch_shape(const StageArgs &a, int rows, int cols, void *stream) {
+  const bool tall = rows == 2 * kTileRows;
+  switch (cols) {
+    case 16: return tall ? launch_one<P, FWD, 16, 2>(a, stream) : launch_one<P, FWD, 16, 1>(a, stream);
+    case 32: return tall ? launch_one<P, FWD, 32, 2>(a, stream) : launch_one<P, FWD, 32, 1>(a, stream);
+    case 64: return tall ? launch_one<P, FWD, 64, 2>(a, stream) : launch_one<P, FWD, 64, 1>(a, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
 
-int launch_fwd_stage(int prec, const StageArgs &a, int bn, void *stream) { return launch(true, prec, a, bn, stream); }
-int launch_bwd_stage(int prec, const StageArgs &a, int bn, void *stream) { return launch(false, prec, a, bn, stream); }
+template <bool FWD>
+static int launch(int prec, const StageArgs &a, int rows, int cols, void *stream) {
+  switch (prec) {
+    case P_F64: return launch_shape<P_F64, FWD>(a, rows, cols, stream);
+    case P_F32: return launch_shape<P_F32, FWD>(a, rows, cols, stream);
+    case P_BF16X2: return launch_shape<P_BF16X2, FWD>(a, rows, cols, stream);
+    case P_BF16X3: return launch_shape<P_BF16X3, FWD>(a, rows, cols, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+int launch_fwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream) {
+  return launch<true>(prec, a, rows, cols, stream);
+}
+int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream) {
+  return launch<false>(prec, a, rows, cols, stream);
+}
 
 // ---------------------------------------------------------------------------
 // Many instances of uneven size per launch.  A batched apply runs one launch
-// per stage position: launch k holds every instance's k-th stage, each
-// workgroup decoding (segment, tile, column tile) from its block index through
-// the segments' first-item offsets.  Stages of one instance are ordered by the
-// launch boundaries, so no workgroup ever waits on another.
+// per stage position (and per group of kSegsPerLaunch instances): launch k
+// holds the k-th stage of its instances, each workgroup decoding (segment,
+// tile, column tile) from its block index through the segments' first-item
+// offsets.  Stages of one instance are ordered by the launch boundaries, so no
+// workgroup ever waits on another.  The segments are launch arguments.
 
-template <int P> struct BatchLds;
-template <> struct BatchLds<P_F64> { static constexpr int bytes = 2 * Tiling<double, 64>::XBUF * 8; };
-template <> struct BatchLds<P_F32> { static constexpr int bytes = 2 * Tiling<float, 64>::XBUF * 4; };
-template <> struct BatchLds<P_BF16X2> { static constexpr int bytes = 2 * 2 * TilingB<2, 64>::XBUF * 2; };
-template <> struct BatchLds<P_BF16X3> { static constexpr int bytes = 2 * 3 * TilingB<3, 64>::XBUF * 2; };
-
-template <int P>
-__device__ __forceinline__ void run_item(const Segment &S, int tix, int ny, void *lds) {
-  if constexpr (P == P_F64 || P == P_F32) {
-    typedef typename std::conditional<P == P_F64, double, float>::type T;
-    T *Xs = static_cast<T *>(lds);
-    if (S.fwd) {
-      if (S.bn == 16) fwd_tile<T, 16>(S.a, tix, ny, Xs);
-      else if (S.bn == 32) fwd_tile<T, 32>(S.a, tix, ny, Xs);
-      else fwd_tile<T, 64>(S.a, tix, ny, Xs);
-    } else {
-      if (S.bn == 16) bwd_tile<T, 16>(S.a, tix, ny, Xs);
-      else if (S.bn == 32) bwd_tile<T, 32>(S.a, tix, ny, Xs);
-      else bwd_tile<T, 64>(S.a, tix, ny, Xs);
-    }
-  } else {
-    constexpr int NTERM = P == P_BF16X2 ? 2 : 3;
-    uint16_t *Xs = static_cast<uint16_t *>(lds);
-    if (S.fwd) {
-      if (S.bn == 16) fwd_tile_bf<NTERM, 16>(S.a, tix, ny, Xs);
-      else if (S.bn == 32) fwd_tile_bf<NTERM, 32>(S.a, tix, ny, Xs);
-      else fwd_tile_bf<NTERM, 64>(S.a, tix, ny, Xs);
-    } else {
-      if (S.bn == 16) bwd_tile_bf<NTERM, 16>(S.a, tix, ny, Xs);
-      else if (S.bn == 32) bwd_tile_bf<NTERM, 32>(S.a, tix, ny, Xs);
-      else bwd_tile_bf<NTERM, 64>(S.a, tix, ny, Xs);
-    }
+template <int P, bool FWD>
+__device__ __forceinline__ void run_segment(const Segment &S, int tix, int ny, void *lds) {
+  const bool tall = S.fm == 2;
+  switch (S.bn) {
+    case 16: if (tall) run_tile<P, FWD, 16, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 16, 1>(S.a, tix, ny, lds); break;
+    case 32: if (tall) run_tile<P, FWD, 32, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 32, 1>(S.a, tix, ny, lds); break;
+    default: if (tall) run_tile<P, FWD, 64, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 64, 1>(S.a, tix, ny, lds); break;
   }
 }
 
 template <int P>
-__global__ __launch_bounds__(kNT) void batched_stage_kernel(const Segment *segs, int32_t nseg) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[BatchLds<P>::bytes];
+__global__ __launch_bounds__(kNT) void batched_stage_kernel(SegPack pack) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, 64>::bytes];
   const int64_t g = blockIdx.x;
-  int32_t lo = 0, hi = nseg - 1;  // last segment whose first item is <= g
+  int32_t lo = 0, hi = pack.nseg - 1;  // last segment whose first item is <= g
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
-    if (segs[mid].item0 <= g) lo = mid; else hi = mid - 1;
+    if (pack.s[mid].item0 <= g) lo = mid; else hi = mid - 1;
   }
-  const Segment &S = segs[lo];
+  const Segment &S = pack.s[lo];
   const int64_t t = g - S.item0;
-  run_item<P>(S, (int)(t % S.a.ntiles), (int)(t / S.a.ntiles), lds);
+  const int tix = (int)(t % S.a.ntiles), ny = (int)(t / S.a.ntiles);
+  if (S.fwd) run_segment<P, true>(S, tix, ny, lds);
+  else run_segment<P, false>(S, tix, ny, lds);
 }
 
-int launch_batched_stage(int prec, const Segment *segs_dev, int32_t nseg, int64_t items, void *stream) {
+int launch_batched_stage(int prec, const SegPack &pack, int64_t items, void *stream) {
   if (items == 0) return 0;
   const dim3 grid((unsigned)items);
   switch (prec) {
     case P_F64:
-      hipLaunchKernelGGL((batched_stage_kernel<P_F64>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      hipLaunchKernelGGL((batched_stage_kernel<P_F64>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
       break;
     case P_F32:
-      hipLaunchKernelGGL((batched_stage_kernel<P_F32>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      hipLaunchKernelGGL((batched_stage_kernel<P_F32>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
       break;
     case P_BF16X2:
-      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X2>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X2>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
       break;
     case P_BF16X3:
-      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X3>), grid, dim3(kNT), 0, (hipStream_t)stream, segs_dev, nseg);
+      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X3>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
       break;
     default: return (int)hipErrorInvalidValue;
   }

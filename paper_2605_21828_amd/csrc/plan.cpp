@@ -50,8 +50,8 @@ float bf16_to_f32(uint16_t h) {
 struct StageDesc {
   int kind;   // 0: level 0 (reads c), 1: transfer level, 2: final (writes f through perm_x)
   int level;
-  int64_t fjob0, nfjob, ftile0, nftile;
-  int64_t bjob0, nbjob, btile0, nbtile;
+  int64_t fjob0, nfjob, bjob0, nbjob;
+  int64_t ftile0[2], nftile[2], btile0[2], nbtile[2];  // tile lists for 64- and 128-row tiles
 };
 
 }  // namespace
@@ -75,7 +75,8 @@ struct bfmht_plan {
   std::vector<unsigned char> staging;
   char *dev = nullptr;
   bool uploaded = false;
-  std::vector<int32_t> bn[2];  // per-stage tile width override (0 = by nrhs), [0] forward, [1] transposed
+  // per-stage tile shape, [0] forward, [1] transposed: rows 64 or 128, cols 16/32/64 or 0 (by nrhs)
+  std::vector<int32_t> rows[2], cols[2];
 };
 
 namespace {
@@ -214,13 +215,12 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
   std::vector<FwdJob> fj;
   std::vector<BwdJob> bj;
   std::vector<Tile> tiles;
-  const int BM = kTileRows;
   // Workgroups of one launch go to the 8 XCDs round robin (workgroup b to XCD
   // b % 8), each XCD with its own L2.  Jobs are packed into 8 bins by cost
   // (longest first), each bin's tiles keep their job's tiles together so the
   // job's right-hand-side rows are fetched into one L2, and the bins are
   // interleaved so bin x lands on XCD x; short bins are padded with empty tiles.
-  auto order = [&](std::vector<std::pair<int64_t, int64_t>> jobs_cost_rows, int64_t job0) {
+  auto order = [&](const std::vector<std::pair<int64_t, int64_t>> &jobs_cost_rows, int BM) {
     const int X = 8;
     std::vector<int64_t> idx(jobs_cost_rows.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int64_t)i;
@@ -231,12 +231,12 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     std::vector<std::vector<Tile>> bins(X);
     std::vector<int64_t> load(X, 0);
     for (int64_t j : idx) {
-      const int64_t rows = jobs_cost_rows[j].second;
-      if (rows <= 0) continue;
+      const int64_t nrows = jobs_cost_rows[j].second;
+      if (nrows <= 0) continue;
       int x = 0;
       for (int y = 1; y < X; ++y)
         if (load[y] < load[x]) x = y;
-      for (int32_t m0 = 0; m0 < rows; m0 += BM) {
+      for (int32_t m0 = 0; m0 < nrows; m0 += BM) {
         bins[x].push_back({(int32_t)j, m0});
         load[x] += std::max<int64_t>(jobs_cost_rows[j].first, 1);
       }
@@ -246,24 +246,27 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     const size_t start = tiles.size();
     for (size_t s = 0; s < len; ++s)
       for (int x = 0; x < X; ++x) tiles.push_back(s < bins[x].size() ? bins[x][s] : Tile{-1, 0});
-    (void)job0;
     return (int64_t)(tiles.size() - start);
   };
   auto add_ftiles = [&](StageDesc &s) {
-    s.ftile0 = (int64_t)tiles.size();
     std::vector<std::pair<int64_t, int64_t>> jc;
     for (int64_t t = s.fjob0; t < s.fjob0 + s.nfjob; ++t) jc.push_back({fj[t].w_off < 0 ? 1 : fj[t].K, fj[t].M});
-    s.nftile = order(jc, s.fjob0);
+    for (int h = 0; h < 2; ++h) {
+      s.ftile0[h] = (int64_t)tiles.size();
+      s.nftile[h] = order(jc, kTileRows << h);
+    }
   };
   auto add_btiles = [&](StageDesc &s) {
-    s.btile0 = (int64_t)tiles.size();
     std::vector<std::pair<int64_t, int64_t>> jc;
     for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t) {
       int64_t cost = 1;
       for (int c = 0; c < bj[t].nc; ++c) cost += bj[t].c[c].M;
       jc.push_back({cost, bj[t].K});
     }
-    s.nbtile = order(jc, s.bjob0);
+    for (int h = 0; h < 2; ++h) {
+      s.btile0[h] = (int64_t)tiles.size();
+      s.nbtile[h] = order(jc, kTileRows << h);
+    }
   };
   auto cons_of = [&](int lvl, int64_t q) -> Cons {
     Cons c;
@@ -337,8 +340,10 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     add_ftiles(s);
     add_btiles(s);
   }
-  p->bn[0].assign(p->stages.size(), 0);
-  p->bn[1].assign(p->stages.size(), 0);
+  for (int d = 0; d < 2; ++d) {
+    p->rows[d].assign(p->stages.size(), kTileRows);
+    p->cols[d].assign(p->stages.size(), 0);
+  }
 
   // Device layout.
   int64_t cur = 0;
@@ -450,7 +455,7 @@ int32_t vec_ok(const void *src, int64_t ld, int64_t esz) {
   return (((uintptr_t)src) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
 }
 
-StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
+StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h) {
   StageArgs a{};
   const int64_t *po = fwd ? p->off_pool : p->off_tpool;
   a.pool = p->dev + po[0];
@@ -458,12 +463,12 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
   a.pool_lo2 = p->nterms > 2 ? p->dev + po[2] : nullptr;
   if (fwd) {
     a.jobs = p->dev + p->off_fjobs + s.fjob0 * (int64_t)sizeof(FwdJob);
-    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.ftile0;
-    a.ntiles = (int32_t)s.nftile;
+    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.ftile0[h];
+    a.ntiles = (int32_t)s.nftile[h];
   } else {
     a.jobs = p->dev + p->off_bjobs + s.bjob0 * (int64_t)sizeof(BwdJob);
-    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0;
-    a.ntiles = (int32_t)s.nbtile;
+    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0[h];
+    a.ntiles = (int32_t)s.nbtile[h];
   }
   a.rowmap = s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
   return a;
@@ -471,9 +476,9 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd) {
 
 // Arguments of stage s of one apply of plan p (forward or transposed) between
 // user buffers in/out and the two level buffers buf[0], buf[1].
-StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, const void *in, int64_t ldin, void *out,
-                   int64_t ldout, int32_t nrhs, char *const buf[2]) {
-  StageArgs a = base_args(p, s, fwd);
+StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, int rows, const void *in, int64_t ldin,
+                   void *out, int64_t ldout, int32_t nrhs, char *const buf[2]) {
+  StageArgs a = base_args(p, s, fwd, rows == 2 * kTileRows ? 1 : 0);
   a.nrhs = nrhs;
   if (fwd) {
     // stage l reads level l-1 (or c) and writes level l (or f)
@@ -486,6 +491,12 @@ StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, const void
   }
   a.vec = vec_ok(a.src, a.lds, p->esz);
   return a;
+}
+
+// Tile width: an explicit 16/32/64, or the smallest that covers nrhs.
+int pick_cols(int cols, int nrhs) {
+  if (cols == 16 || cols == 32 || cols == 64) return cols;
+  return nrhs <= 16 ? 16 : (nrhs <= 32 ? 32 : 64);
 }
 
 int64_t level_buffer_bytes(const bfmht_plan *p, int32_t nrhs) {
@@ -501,19 +512,15 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
   for (int k = 0; k < S; ++k) {
     const int si = fwd ? k : S - 1 - k;
     const StageDesc &s = p->stages[si];
-    StageArgs a = stage_io(p, s, fwd, in, ldin, out, ldout, nrhs, buf);
-    const int bn = p->bn[fwd ? 0 : 1][si];
-    const int e = fwd ? launch_fwd_stage(p->prec, a, bn, stream) : launch_bwd_stage(p->prec, a, bn, stream);
+    const int d = fwd ? 0 : 1;
+    const int rows = p->rows[d][si], cols = pick_cols(p->cols[d][si], nrhs);
+    StageArgs a = stage_io(p, s, fwd, rows, in, ldin, out, ldout, nrhs, buf);
+    const int e = fwd ? launch_fwd_stage(p->prec, a, rows, cols, stream) : launch_bwd_stage(p->prec, a, rows, cols, stream);
     if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
   }
   return BFMHT_OK;
 }
 
-
-int pick_cols(int bn, int nrhs) {
-  if (bn == 16 || bn == 32 || bn == 64) return bn;
-  return nrhs <= 16 ? 16 : (nrhs <= 32 ? 32 : 64);
-}
 
 }  // namespace
 
@@ -531,24 +538,29 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t l
 
 int32_t bfmht_plan_num_stages(const bfmht_plan *p) { return p ? (int32_t)p->stages.size() : -1; }
 
-bfmht_status bfmht_plan_set_tile_cols(bfmht_plan *p, int32_t transpose, int32_t stage, int32_t cols) {
+bfmht_status bfmht_plan_set_tile(bfmht_plan *p, int32_t transpose, int32_t stage, int32_t rows, int32_t cols) {
   if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
   if (stage < 0 || stage >= (int32_t)p->stages.size()) return fail(BFMHT_EINVAL, "stage out of range");
+  if (rows != kTileRows && rows != 2 * kTileRows) return fail(BFMHT_EINVAL, "tile rows must be 64 or 128");
   if (cols != 0 && cols != 16 && cols != 32 && cols != 64) return fail(BFMHT_EINVAL, "tile columns must be 0, 16, 32 or 64");
-  p->bn[transpose ? 1 : 0][stage] = cols;
+  p->rows[transpose ? 1 : 0][stage] = rows;
+  p->cols[transpose ? 1 : 0][stage] = cols;
   return BFMHT_OK;
 }
 
-int32_t bfmht_plan_get_tile_cols(const bfmht_plan *p, int32_t transpose, int32_t stage) {
-  if (!p || stage < 0 || stage >= (int32_t)p->stages.size()) return -1;
-  return p->bn[transpose ? 1 : 0][stage];
+bfmht_status bfmht_plan_get_tile(const bfmht_plan *p, int32_t transpose, int32_t stage, int32_t *rows, int32_t *cols) {
+  if (!p || !rows || !cols) return fail(BFMHT_EINVAL, "NULL argument");
+  if (stage < 0 || stage >= (int32_t)p->stages.size()) return fail(BFMHT_EINVAL, "stage out of range");
+  *rows = p->rows[transpose ? 1 : 0][stage];
+  *cols = p->cols[transpose ? 1 : 0][stage];
+  return BFMHT_OK;
 }
 
 // ---- batched ----
 
 namespace {
 struct BatchLayout {
-  int64_t segs = 0, bufs = 0, total = 0;
+  int64_t total = 0;
   int32_t nseg = 0;
   std::vector<int64_t> buf_off;  // per instance
 };
@@ -564,9 +576,7 @@ bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const i
     if (plans[i]->prec != plans[0]->prec) return fail(BFMHT_EINVAL, "plans of a batch must share one precision");
     if (nrhs[i] > 0) L.nseg += (int32_t)plans[i]->stages.size();
   }
-  L.segs = 0;
-  L.bufs = align_up((int64_t)L.nseg * (int64_t)sizeof(Segment), 256);
-  int64_t cur = L.bufs;
+  int64_t cur = 0;
   for (int32_t i = 0; i < count; ++i) {
     L.buf_off[i] = cur;
     if (nrhs[i] > 0) cur += 2 * level_buffer_bytes(plans[i], nrhs[i]);
@@ -607,44 +617,46 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
     for (int k = 0; k < S; ++k) {
       const int si = fwd ? k : S - 1 - k;
       Segment sg{};
-      sg.a = stage_io(p, p->stages[si], fwd, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);
+      const int d = fwd ? 0 : 1;
+      const int rows = p->rows[d][si];
+      sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);
       sg.fwd = fwd ? 1 : 0;
-      sg.bn = pick_cols(p->bn[fwd ? 0 : 1][si], nrhs[i]);
+      sg.fm = rows / kTileRows;
+      sg.bn = pick_cols(p->cols[d][si], nrhs[i]);
       sg.ny = (nrhs[i] + sg.bn - 1) / sg.bn;
       sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
       per[i].push_back(sg);
     }
     maxS = std::max(maxS, per[i].size());
   }
-  // Launch k runs the k-th stage of every instance; segments of one launch are
-  // contiguous in the table, segments without items are left out.
-  std::vector<Segment> segs;
-  std::vector<std::pair<size_t, int64_t>> launches;  // (first segment, items)
+  // Launch k runs the k-th stage of every instance (in groups of at most
+  // kSegsPerLaunch, passed as launch arguments); segments without items are
+  // left out.
   for (size_t k = 0; k < maxS; ++k) {
-    const size_t first = segs.size();
+    SegPack pack{};
     int64_t item = 0;
+    auto flush = [&]() -> bfmht_status {
+      if (pack.nseg == 0) return BFMHT_OK;
+      if (item >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
+      const int rc = launch_batched_stage(plans[0]->prec, pack, item, stream);
+      if (rc) return fail(BFMHT_EHIP, std::string("batched launch: ") + hipGetErrorString((hipError_t)rc));
+      pack.nseg = 0;
+      item = 0;
+      return BFMHT_OK;
+    };
     for (int32_t i = 0; i < count; ++i) {
       if (k >= per[i].size() || per[i][k].nitems == 0) continue;
       Segment sg = per[i][k];
       sg.item0 = item;
       item += sg.nitems;
-      segs.push_back(sg);
+      pack.s[pack.nseg++] = sg;
+      if (pack.nseg == kSegsPerLaunch) {
+        st = flush();
+        if (st != BFMHT_OK) return st;
+      }
     }
-    if (item >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
-    launches.push_back({first, item});
-  }
-  char *w = static_cast<char *>(ws);
-  if (!segs.empty()) {
-    hipError_t e = hipMemcpyAsync(w + L.segs, segs.data(), segs.size() * sizeof(Segment), hipMemcpyHostToDevice,
-                                  (hipStream_t)stream);
-    if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("batch table upload: ") + hipGetErrorString(e));
-  }
-  const Segment *dsegs = reinterpret_cast<const Segment *>(w + L.segs);
-  for (size_t k = 0; k < launches.size(); ++k) {
-    const size_t first = launches[k].first;
-    const size_t nk = (k + 1 < launches.size() ? launches[k + 1].first : segs.size()) - first;
-    const int rc = launch_batched_stage(plans[0]->prec, dsegs + first, (int32_t)nk, launches[k].second, stream);
-    if (rc) return fail(BFMHT_EHIP, std::string("batched launch: ") + hipGetErrorString((hipError_t)rc));
+    st = flush();
+    if (st != BFMHT_OK) return st;
   }
   return BFMHT_OK;
 }

@@ -90,7 +90,7 @@ def test_grid_instances_vs_inverse_dft(gpu):
         assert od.rel_err_cols(_np(y), ref)[0] <= 1e-5
 
 
-def test_tile_width_does_not_change_results(gpu, instances):
+def test_tile_shape_does_not_change_results(gpu, instances):
     from paper_2605_21828_amd import bfmht as B
     from paper_2605_21828_amd.bfmht import Plan
     fs = instances[5]
@@ -101,15 +101,35 @@ def test_tile_width_does_not_change_results(gpu, instances):
     S = B.bfmht_plan_num_stages(p.handle)
     assert S == int(fs["L"]) + 2
     for k in range(S):
-        B.bfmht_plan_set_tile_cols(p.handle, 0, k, (16, 32, 64)[k % 3])
-        B.bfmht_plan_set_tile_cols(p.handle, 1, k, (64, 16, 32)[k % 3])
-    assert B.bfmht_plan_get_tile_cols(p.handle, 0, 1) == 32
+        B.bfmht_plan_set_tile(p.handle, 0, k, (64, 128)[k % 2], (16, 32, 64)[k % 3])
+        B.bfmht_plan_set_tile(p.handle, 1, k, (128, 64)[k % 2], (64, 16, 32)[k % 3])
+    assert B.bfmht_plan_get_tile(p.handle, 0, 1) == (128, 32)
     assert np.array_equal(_np(p.apply(x)), base_y)
     assert np.array_equal(_np(p.apply_t(f)), base_g)
     with pytest.raises(B.BfmhtError):
-        B.bfmht_plan_set_tile_cols(p.handle, 0, 0, 48)
+        B.bfmht_plan_set_tile(p.handle, 0, 0, 64, 48)
     with pytest.raises(B.BfmhtError):
-        B.bfmht_plan_set_tile_cols(p.handle, 0, S, 16)
+        B.bfmht_plan_set_tile(p.handle, 0, 0, 96, 16)
+    with pytest.raises(B.BfmhtError):
+        B.bfmht_plan_set_tile(p.handle, 0, S, 64, 16)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x2", "bf16x3"])
+def test_tall_tiles_match_oracle(gpu, instances, prec):
+    """128-row tiles (two 16-row blocks per wave) in every stage, all precisions."""
+    from paper_2605_21828_amd import bfmht as B
+    from paper_2605_21828_amd.bfmht import Plan
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5, "bf16x2": 2e-4}[prec]
+    for fs, case in zip(instances[:6], CASES[:6]):
+        b = max(1, case[5])
+        p = Plan(fs, prec, max_nrhs=b)
+        for k in range(B.bfmht_plan_num_stages(p.handle)):
+            B.bfmht_plan_set_tile(p.handle, 0, k, 128, 0)
+            B.bfmht_plan_set_tile(p.handle, 1, k, 128, 0)
+        rng = np.random.default_rng(case[0])
+        c, f = rng.standard_normal((p.m, b)), rng.standard_normal((p.n, b))
+        assert od.rel_err_cols(_np(p.apply(_t(c, _dt(prec)))), ob.apply(fs, c))[0] <= tol, case
+        assert od.rel_err_cols(_np(p.apply_t(_t(f, _dt(prec)))), ob.apply_transpose(fs, f))[0] <= tol, case
 
 
 @pytest.mark.skip(reason="single persistent launch with inter-workgroup waits is switched off: two runs "
@@ -130,8 +150,9 @@ def test_autotune_sets_widths_and_keeps_results(gpu, instances, tmp_path):
     cfg = autotune.tune_plan(p, fs, 100, reps=3, cache_path=str(tmp_path / "t.json"))
     S = B.bfmht_plan_num_stages(p.handle)
     assert len(cfg["fwd"]) == S and len(cfg["bwd"]) == S
-    assert all(w in (0, 16, 32, 64) for w in cfg["fwd"] + cfg["bwd"])
-    assert [B.bfmht_plan_get_tile_cols(p.handle, 0, k) for k in range(S)] == cfg["fwd"]
+    assert all(tuple(s) in autotune.SHAPES + [(64, 0)] for s in cfg["fwd"] + cfg["bwd"])
+    q_cfg = None
+    assert [B.bfmht_plan_get_tile(p.handle, 0, k) for k in range(S)] == [tuple(s) for s in cfg["fwd"]]
     assert np.array_equal(_np(p.apply(x)), base)
     # a second plan of the same shape picks the cached choice up
     q = Plan(fs, "f32", max_nrhs=100)
