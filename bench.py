@@ -50,6 +50,45 @@ def measured_traffic(workload):
     return d["fwd_per_dispatch"]["hbm_bytes"]
 
 
+# MI355X spec-sheet peaks: dense MFMA TFLOP/s per arithmetic type and HBM GB/s.
+MFMA_PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
+HBM_PEAK = 8000.0
+SPLIT_PRODUCTS = {"f64": 1, "f32": 1, "bf16x2": 3, "bf16x3": 6}
+FACTOR_BYTES = {"f64": 8, "f32": 4, "bf16x2": 4, "bf16x3": 6}
+
+
+def roofline_for(prec, F, n, m, b, apply_ms, launches):
+    """Roofline of one apply: the binding one of the MFMA time (executed flops,
+    split products counted, at the type's peak) and the HBM time (algorithmic
+    bytes: stored factors plus inputs and outputs).  `achieved` is that
+    quantity per launch over the average launch duration."""
+    io = (8 if prec == "f64" else 4) * (n + m) * b
+    alg_bytes = FACTOR_BYTES[prec] * F + io
+    exec_flops = 2.0 * F * b * SPLIT_PRODUCTS[prec]
+    t_mfma = exec_flops / (MFMA_PEAK[prec] * 1e12)
+    t_hbm = alg_bytes / (HBM_PEAK * 1e9)
+    t = apply_ms * 1e-3
+    if t_mfma >= t_hbm:
+        r = {"bound": "mfma", "achieved": exec_flops / t / 1e12, "peak": MFMA_PEAK[prec], "unit": "TFLOP/s",
+             "per_launch_flops": exec_flops / launches, "flops_counted": "2 F b x split products"}
+    else:
+        r = {"bound": "hbm", "achieved": alg_bytes / t / 1e9, "peak": HBM_PEAK, "unit": "GB/s",
+             "per_launch_alg_bytes": alg_bytes / launches}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    r["avg_launch_ms"] = apply_ms / launches
+    r["t_roof_ms"] = max(t_mfma, t_hbm) * 1e3
+    return r
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] or [1]))
+    except Exception:
+        return int(os.cpu_count() or 1)
+
+
 def event_time(fn, reps, torch):
     """Average milliseconds of fn() over reps, measured with HIP events on the current stream."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -61,36 +100,43 @@ def event_time(fn, reps, torch):
     return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(fs, pts, c_host, f_host, out32, g32, rows, cols, lam):
+def cpu_baseline(fs, pts, c_host, f_host, out32, g32, rows, cols, lam, variant_outputs=None):
     """The oracle as it stands, timed on the host cores, plus the accuracy check.
 
     Times the oracle's butterfly apply and its transpose (O2, NumPy) on a
-    bounded sample of 4 right-hand sides of the same factors; reports
+    bounded sample of whole passes over the same factors and RHS; reports
     RHS*points/s over both directions.  Then measures the GPU FP32 results
-    against the dense FP64 transform (O1) on sampled rows and columns.
+    (and any precision variant's) against the dense FP64 transform (O1) on
+    sampled rows and columns.
     """
     from oracle import butterfly as ob
     from oracle import dense as od
     from oracle import modes as om
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count()
-    b_s = 4
+    cores = _blas_threads()
+    # Bounded sample: whole passes over all RHS until about 10 s of host work.
+    b_s = c_host.shape[1]
     t0 = time.time()
-    ob.apply(fs, c_host[:, :b_s])
-    ob.apply_transpose(fs, f_host[:, :b_s])
+    passes = 0
+    while passes == 0 or (time.time() - t0 < 10.0 and passes < 16):
+        ob.apply(fs, c_host[:, :b_s])
+        ob.apply_transpose(fs, f_host[:, :b_s])
+        passes += 1
     dt = time.time() - t0
     n = int(fs["n"])
     md = om.fourier_modes(int(fs["m"]))
-    err_f = od.rel_err_cols(out32[rows], od.fourier_synthesis_rows(pts, md, rows, c_host))[0]
-    err_g = od.rel_err_cols(g32[cols], od.fourier_analysis_cols(pts, md, cols, f_host))[0]
-    base = {"value": 2.0 * n * b_s / dt, "unit": "RHS*points/s", "cores": int(cores), "kind": "oracle",
-            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors on %d of the RHS, %.1f s"
-                      % (b_s, dt)}
-    return base, {"synthesis_rows_sampled": len(rows), "synthesis_rel_err": err_f,
-                  "analysis_cols_sampled": len(cols), "analysis_rel_err": err_g}
+    ref_f = od.fourier_synthesis_rows(pts, md, rows, c_host)
+    ref_g = od.fourier_analysis_cols(pts, md, cols, f_host)
+    err_f = od.rel_err_cols(out32[rows], ref_f)[0]
+    err_g = od.rel_err_cols(g32[cols], ref_g)[0]
+    base = {"value": 2.0 * n * b_s * passes / dt, "unit": "RHS*points/s", "cores": int(cores), "kind": "oracle",
+            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors, %d pass(es) over all %d "
+                      "RHS, %.1f s" % (passes, b_s, dt)}
+    acc = {"synthesis_rows_sampled": len(rows), "synthesis_rel_err": err_f,
+           "analysis_cols_sampled": len(cols), "analysis_rel_err": err_g}
+    for prec, (yv, gv) in (variant_outputs or {}).items():
+        acc["%s_synthesis_rel_err" % prec] = od.rel_err_cols(yv[rows], ref_f)[0]
+        acc["%s_analysis_rel_err" % prec] = od.rel_err_cols(gv[cols], ref_g)[0]
+    return base, acc
 
 
 def bench_batched(args):
@@ -193,7 +239,7 @@ def bench_sphere(args):
     c = wl.coefficients(spec["wid"], m, b)
     fv = wl.values(spec["wid"], n, b)
     dev = torch.device("cuda:0")
-    main = args.precision or "bf16x2"
+    main = args.precision or "bf16x3"
     rec = {}
     outs = {}
     for prec in [main] + [p for p in ("bf16x3", "bf16x2", "f32", "f64") if p != main]:
@@ -202,6 +248,10 @@ def bench_sphere(args):
         ct, ft = torch.tensor(c, dtype=dt, device=dev), torch.tensor(fv, dtype=dt, device=dev)
         y = torch.empty((n, b), dtype=dt, device=dev)
         g = torch.empty((m, b), dtype=dt, device=dev)
+        shapes = None
+        if not args.no_tune:
+            from paper_2605_21828_amd.autotune import tune_plan
+            shapes = tune_plan(p, fs, b, use_cache=args.cache, log=log)
 
         def step():
             p.apply(ct, out=y)
@@ -218,7 +268,7 @@ def bench_sphere(args):
         t_f = event_time(lambda: p.apply(ct, out=y), reps, torch)
         t_b = event_time(lambda: p.apply_t(ft, out=g), reps, torch)
         outs[prec] = (y.double().cpu().numpy(), g.double().cpu().numpy())
-        rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b}
+        rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b, "tile_shapes": shapes}
         log("%s step %.3f ms" % (prec, ms))
         del p, ct, ft, y, g
         torch.cuda.empty_cache()
@@ -226,21 +276,24 @@ def bench_sphere(args):
         from oracle import butterfly as ob
         from oracle import dense as od
         t0 = time.time()
-        ob.apply(fs, c[:, :8])
-        ob.apply_transpose(fs, fv[:, :8])
+        passes = 0
+        while passes == 0 or (time.time() - t0 < 10.0 and passes < 16):
+            ob.apply(fs, c)
+            ob.apply_transpose(fs, fv)
+            passes += 1
         dt_cpu = time.time() - t0
         ref_y, ref_g = Phi @ c, Phi.T @ fv
         for prec, (y, g) in outs.items():
             rec[prec]["synthesis_rel_err_vs_dense_fp64"] = od.rel_err_cols(y, ref_y)[0]
             rec[prec]["analysis_rel_err_vs_dense_fp64"] = od.rel_err_cols(g, ref_g)[0]
-        base = {"value": 2.0 * n * 8 / dt_cpu, "unit": "RHS*points/s", "cores": os.cpu_count(), "kind": "oracle",
-                "sample": "oracle butterfly apply + transpose (NumPy FP64) on 8 of the 256 RHS, %.1f s" % dt_cpu}
+        base = {"value": 2.0 * n * b * passes / dt_cpu, "unit": "RHS*points/s", "cores": _blas_threads(),
+                "kind": "oracle",
+                "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors, %d pass(es) over "
+                          "all %d RHS, %.1f s" % (passes, b, dt_cpu)}
     else:
         base = None
     t_main = rec[main]["apply_ms"]
-    nterm = {"bf16x2": 3, "bf16x3": 6}.get(main, 1)
-    peak = 2500.0 if main.startswith("bf16") else (157.3 if main == "f32" else 78.6)
-    achieved = 2.0 * F * b * nterm / (t_main * 1e-3) / 1e12
+    roof = roofline_for(main, F, n, m, b, t_main, launches=int(fs["L"]) + 2)
     res = {
         "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
         "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
@@ -248,9 +301,7 @@ def bench_sphere(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main, "data": "synthetic",
         "config": {"workload": "sphere40962", "n": n, "m": m, "nrhs": b, "leaf": spec["leaf"], "tol": spec["tol"],
                    "L": int(fs["L"]), "step": "apply + apply_transpose"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "note": "executed MFMA flops (split products counted) over the apply"},
+        "roofline": roof,
         "cpu_baseline": base,
         "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "precisions": rec},
     }
@@ -362,6 +413,7 @@ def main():
     # reference and accuracy anchor) and the BF16 split products.
     variants = [v for v in args.variants.split(",") if v]
     y64 = None
+    variant_outputs = {}
     for prec in variants:
         log("uploading %s plan" % prec)
         pv = Plan(fs, prec, max_nrhs=b, device=dev)
@@ -370,6 +422,10 @@ def main():
         fv = f32.to(dt) if prec != "f64" else torch.tensor(f_host, dtype=dt, device=dev)
         yv = torch.empty((n, b), dtype=dt, device=dev)
         gv = torch.empty((m, b), dtype=dt, device=dev)
+        shapes = None
+        if not args.no_tune:
+            from paper_2605_21828_amd.autotune import tune_plan
+            shapes = tune_plan(pv, fs, b, use_cache=args.cache, log=log)
         for _ in range(2):
             pv.apply(cv, out=yv)
             pv.apply_t(fv, out=gv)
@@ -377,11 +433,14 @@ def main():
         t_b = event_time(lambda: pv.apply_t(fv, out=gv), reps, torch)
         rec = {"apply_ms": t_f, "apply_transpose_ms": t_b,
                "speedup_vs_fp32": (ms_fwd + ms_bwd) / (t_f + t_b),
-               "plan_device_GB": pv.device_bytes / 1e9}
+               "plan_device_GB": pv.device_bytes / 1e9, "tile_shapes": shapes,
+               "roofline": roofline_for(prec, F, n, m, b, t_f, launches)}
         if prec == "f64":
             y64 = yv.clone()
-        elif y64 is not None:
-            rec["rel_err_vs_fp64_gpu"] = float(torch.linalg.norm(yv.double() - y64) / torch.linalg.norm(y64))
+        else:
+            if y64 is not None:
+                rec["rel_err_vs_fp64_gpu"] = float(torch.linalg.norm(yv.double() - y64) / torch.linalg.norm(y64))
+            variant_outputs[prec] = (yv.double().cpu().numpy(), gv.double().cpu().numpy())
         variants_out[prec] = rec
         del pv, cv, fv, yv, gv
         torch.cuda.empty_cache()
@@ -398,7 +457,7 @@ def main():
         cols = wl.sample_indices(w["wid"], m, 2048, stream=4)
         out_np = y32.double().cpu().numpy()
         g_np = g32.double().cpu().numpy()
-        base, acc = cpu_baseline(fs, pts, c_host, f_host, out_np, g_np, rows, cols, lam)
+        base, acc = cpu_baseline(fs, pts, c_host, f_host, out_np, g_np, rows, cols, lam, variant_outputs)
         result_extra.update(acc)
 
     bound, peak, unit = PEAK["f32"]
@@ -415,7 +474,7 @@ def main():
                      "frac": achieved / peak, "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per launch",
                      "alg_bytes_per_launch": alg_bytes32 / launches,
-                     "kernel": "fwd_stage_kernel<float,64> (all stage launches of one FP32 apply)",
+                     "kernel": "stage_kernel<P_F32, forward> (all stage launches of one FP32 apply)",
                      "per_launch_alg_flops": flops / launches,
                      "avg_launch_ms": ms_fwd / launches},
         "cpu_baseline": base,

@@ -52,6 +52,11 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
 __device__ __forceinline__ int acc_row(float, int lane, int i) { return 4 * (lane >> 4) + i; }
 __device__ __forceinline__ int acc_row(double, int lane, int i) { return 4 * i + (lane >> 4); }
 
+// Number of this wave's FM 16-row blocks that hold at least one row of the job
+// (`left` = job rows from the wave's first row on); wave-uniform.
+template <int FM>
+__device__ __forceinline__ int active_blocks(int left) { return left <= 0 ? 0 : min(FM, (left + 15) >> 4); }
+
 constexpr int kWaves = 4;
 constexpr int kNT = 64 * kWaves;
 static_assert(kTileRows == 16 * kWaves, "one 16-row MFMA block per wave at FM = 1");
@@ -148,9 +153,10 @@ __device__ __forceinline__ void load_w(T *wr, const T *wrow, int ldw, int k0, in
 }
 
 // acc += W_chunk (this wave's FM x 16 rows) * X_chunk (all BN columns).
+// Blocks past the job's last row (`nact` active blocks, wave-uniform) are skipped.
 template <typename T, int BN, int FM>
 __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16], const T (*wr)[Cfg<T>::KC / 4],
-                                          const T *Xs, int lrow, int lg) {
+                                          const T *Xs, int lrow, int lg, int nact) {
   typedef Tiling<T, BN> Tl;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
@@ -158,8 +164,10 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
     copy_vec<T, Tl::KL>(b, &Xs[(fn * 16 + lrow) * Tl::XS + Tl::KL * lg]);
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
+      if (fm < nact) {
 #pragma unroll
-      for (int t = 0; t < Tl::KL; ++t) acc[fm][fn] = mfma16x16x4(wr[fm][t], b[t], acc[fm][fn]);
+        for (int t = 0; t < Tl::KL; ++t) acc[fm][fn] = mfma16x16x4(wr[fm][t], b[t], acc[fm][fn]);
+      }
   }
 }
 
@@ -169,13 +177,14 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
 template <typename T, int BN, int FM>
 __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int ldw,
                                            int nk, const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
-                                           T *Xs, int tid, int lrow, int lg) {
+                                           T *Xs, int tid, int lrow, int lg, int nact) {
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
   T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(wA[fm], wrow[fm], ldw, 0, lg);
+  for (int fm = 0; fm < FM; ++fm)
+    if (fm < nact) load_w<T, BN>(wA[fm], wrow[fm], ldw, 0, lg);
   load_x<T, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
   store_x<T, BN>(Xs, xB, tid);
   __syncthreads();
@@ -183,10 +192,11 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
     const bool more = c + 1 < nchunk;
     if (more) {
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
+      for (int fm = 0; fm < FM; ++fm)
+        if (fm < nact) load_w<T, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
       load_x<T, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
     }
-    mma_chunk<T, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    mma_chunk<T, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
     if (more) {
       store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
 #pragma unroll
@@ -211,8 +221,9 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
     return;
   }
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
   const int rbase = tile.m0 + wave * 16 * FM;
+  const int nact = active_blocks<FM>(J.M - rbase);
   const T *wrow[FM];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -222,7 +233,7 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  gemm_block<T, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+  gemm_block<T, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
   T *dst = static_cast<T *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -246,21 +257,24 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
   const int rbase = tile.m0 + wave * 16 * FM;
+  const int nact = active_blocks<FM>(J.K - rbase);
   typename Cfg<T>::acc_t acc[FM][Tl::FN];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  for (int ci = 0; ci < J.nc; ++ci) {
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
+    if (ci >= J.nc) break;
     const Cons C = J.c[ci];
     if (C.wt_off < 0) continue;
     const T *wrow[FM];
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
       wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
-    gemm_block<T, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
+    gemm_block<T, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
@@ -274,8 +288,9 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
         const int gc = n0 + fn * 16 + lrow;
         if (gr < J.K && gc < a.nrhs) {
           T v = acc[fm][fn][i];
-          for (int ci = 0; ci < J.nc; ++ci)
-            if (J.c[ci].wt_off < 0) {
+#pragma unroll
+          for (int ci = 0; ci < 2; ++ci)
+            if (ci < J.nc && J.c[ci].wt_off < 0) {
               const int32_t b = J.c[ci].g_row;
               const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
               v += src[srow * a.lds + gc];
@@ -386,7 +401,7 @@ __device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const 
 
 template <int NTERM, int BN, int FM>
 __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*wr)[NTERM][2], const uint16_t *Xs,
-                                             int lrow, int lg) {
+                                             int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
@@ -398,6 +413,7 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
       for (int t = 0; t < NTERM; ++t) b[t] = *reinterpret_cast<const uint4 *>(Xs + t * 2 * Tl::XBUF + off + 8 * h);
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm) {
+        if (fm >= nact) continue;
         // smallest products first
         if constexpr (NTERM == 3) {
           acc[fm][fn] = mfma_bf16(wr[fm][2][h], b[0], acc[fm][fn]);
@@ -417,14 +433,15 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
 template <int NTERM, int BN, int FM>
 __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int ldw, int nk,
                                               const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
-                                              uint16_t *Xs, int tid, int lrow, int lg) {
+                                              uint16_t *Xs, int tid, int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
   uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(wA[fm], wrow[fm], ldw, 0, lg);
+  for (int fm = 0; fm < FM; ++fm)
+    if (fm < nact) load_w_bf<NTERM, BN>(wA[fm], wrow[fm], ldw, 0, lg);
   load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
   store_x_bf<NTERM, BN>(Xs, xB, tid);
   __syncthreads();
@@ -432,10 +449,11 @@ __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_
     const bool more = c + 1 < nchunk;
     if (more) {
 #pragma unroll
-      for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
+      for (int fm = 0; fm < FM; ++fm)
+        if (fm < nact) load_w_bf<NTERM, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
       load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
     }
-    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
     if (more) {
       store_x_bf<NTERM, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
 #pragma unroll
@@ -462,8 +480,9 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
     return;
   }
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
   const int rbase = tile.m0 + wave * 16 * FM;
+  const int nact = active_blocks<FM>(J.M - rbase);
   const uint16_t *wrow[FM][3];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm) {
@@ -477,7 +496,7 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg);
+  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
   float *dst = static_cast<float *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -499,14 +518,17 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
   const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
   const int n0 = ny * BN;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
   const int rbase = tile.m0 + wave * 16 * FM;
+  const int nact = active_blocks<FM>(J.K - rbase);
   v4f acc[FM][Tl::FN];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  for (int ci = 0; ci < J.nc; ++ci) {
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
+    if (ci >= J.nc) break;
     const Cons C = J.c[ci];
     if (C.wt_off < 0) continue;
     const uint16_t *wrow[FM][3];
@@ -517,7 +539,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
       wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
       wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg);
+    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
@@ -531,8 +553,9 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
         const int gc = n0 + fn * 16 + lrow;
         if (gr < J.K && gc < a.nrhs) {
           float v = acc[fm][fn][i];
-          for (int ci = 0; ci < J.nc; ++ci)
-            if (J.c[ci].wt_off < 0) {
+#pragma unroll
+          for (int ci = 0; ci < 2; ++ci)
+            if (ci < J.nc && J.c[ci].wt_off < 0) {
               const int32_t b = J.c[ci].g_row;
               const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
               v += src[srow * a.lds + gc];
@@ -564,17 +587,24 @@ __device__ __forceinline__ void run_tile(const StageArgs &a, int tix, int ny, vo
   }
 }
 
+// Workgroup b runs on XCD b % 8.  The tile list interleaves 8 bins (tile
+// 8 s + x belongs to bin x), so block b takes bin x = b % 8 and walks that
+// bin's tiles with the ny column tiles of each tile back to back: the column
+// tiles of one factor tile share its rows through that XCD's L2.
 template <int P, bool FWD, int BN, int FM>
-__global__ __launch_bounds__(kNT) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(kNT) void stage_kernel(StageArgs a, int ny) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, BN>::bytes];
-  run_tile<P, FWD, BN, FM>(a, blockIdx.x, blockIdx.y, lds);
+  const int b = blockIdx.x, x = b & 7, s = b >> 3;
+  run_tile<P, FWD, BN, FM>(a, (s / ny) * 8 + x, s % ny, lds);
 }
 
 template <int P, bool FWD, int BN, int FM>
 static int launch_one(const StageArgs &a, void *stream) {
   if (a.ntiles == 0) return 0;
-  dim3 grid(a.ntiles, (a.nrhs + BN - 1) / BN);
-  hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM>), grid, dim3(kNT), 0, (hipStream_t)stream, a);
+  if (a.ntiles % 8) return (int)hipErrorInvalidValue;  // tile lists come in whole rounds of 8 bins
+  const int ny = (a.nrhs + BN - 1) / BN;
+  const dim3 grid((unsigned)((int64_t)a.ntiles * ny));
+  hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM>), grid, dim3(kNT), 0, (hipStream_t)stream, a, ny);
   return (int)hipGetLastError();
 }
 
