@@ -308,6 +308,123 @@ def bench_sphere(args):
     print(json.dumps(res), flush=True)
 
 
+def lsq_checks(fs, pts, c_np, f, grad_np, lam_rows):
+    """Oracle leg of the least-squares workload: the autograd gradient at c
+    against central differences of the oracle's FP64 butterfly loss on 64
+    coordinates and against the dense FP64 2 Phi^T (Phi c - f) of the exact
+    transform on 256 sampled columns; also times the oracle's apply pair."""
+    from oracle import butterfly as ob
+    from oracle import dense as od
+    from oracle import modes as om
+    md_oracle = om.fourier_modes(int(fs["m"]))
+    coords = lam_rows["fd"]
+    cols = lam_rows["cols"]
+    h = 1.0
+    t0 = time.time()
+    E = np.zeros((c_np.size, len(coords)))
+    E[coords, np.arange(len(coords))] = h
+    Yp = ob.apply(fs, c_np[:, None] + E)
+    Ym = ob.apply(fs, c_np[:, None] - E)
+    fd = (np.sum((Yp - f[:, None]) ** 2, axis=0) - np.sum((Ym - f[:, None]) ** 2, axis=0)) / (2 * h)
+    t_fd = time.time() - t0
+    fd_err = float(np.linalg.norm(grad_np[coords] - fd) / np.linalg.norm(fd))
+    t1 = time.time()
+    r = od.fourier_synthesis_all(pts, md_oracle, c_np) - f
+    dense = 2.0 * od.fourier_analysis_cols(pts, md_oracle, cols, r)
+    dense_err = float(np.linalg.norm(grad_np[cols] - dense) / np.linalg.norm(dense))
+    t_dense = time.time() - t1
+    # oracle timing: one butterfly apply + transpose pair at b = 1
+    t2 = time.time()
+    ob.apply(fs, c_np[:, None])
+    ob.apply_transpose(fs, f[:, None])
+    t_pair = time.time() - t2
+    base = {"value": 2.0 * int(fs["n"]) / t_pair, "unit": "RHS*points/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors, one RHS, %.1f s" % t_pair}
+    return base, {"fd_coordinates": len(coords), "fd_rel_err": fd_err, "fd_seconds": t_fd,
+                  "dense_cols_sampled": len(cols), "dense_grad_rel_err": dense_err, "dense_seconds": t_dense}
+
+
+def bench_lsq(args):
+    """Differentiable least-squares fit: 262144 i.i.d. points, 65536 modes, FP32 autograd, 100 GD steps."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.autograd import least_squares_step
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+    from paper_2605_21828_amd.factor.fourier import FourierBlocks, real_modes
+
+    w = wl.WORKLOADS["iid" + args.workload[len("lsq"):]]
+    n, m, wid = w["n"], w["m"], w["wid"]
+    pts = wl.points_for(w)
+    log("building factors: n=%d m=%d leaf=%d tol=%g" % (n, m, w["leaf"], w["tol"]))
+    t0 = time.time()
+    fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
+                                log=lambda s: log("  factor", s))
+    t_build = time.time() - t0
+    F = fio.stored_entries(fs)
+    modes = real_modes(m)
+    lam = (modes[:, 0] ** 2 + modes[:, 1] ** 2).astype(np.float64)
+    c_star = wl.coefficients(wid, m, 1, lam=lam, kind="decay")[:, 0]
+    log("exact right-hand side f = Phi c* + 1e-3 noise")
+    f = FourierBlocks(pts, modes).synthesis(c_star) + 1e-3 * wl.values(wid, n, 1)[:, 0]
+    dev = torch.device("cuda:0")
+    log("uploading FP32 plan (%d stored entries)" % F)
+    plan = Plan(fs, "f32", max_nrhs=1, device=dev)
+    ft = torch.tensor(f, dtype=torch.float32, device=dev)
+    # step size 0.5 / sigma_max^2, sigma_max^2 from 20 power iterations on Phi~^T Phi~
+    v = torch.tensor(wl.coefficients(wid, m, 1, stream=5)[:, 0], dtype=torch.float32, device=dev)
+    for _ in range(20):
+        v = plan.apply_t(plan.apply(v))
+        s2 = torch.linalg.norm(v)
+        v = v / s2
+    lr = 0.5 / float(s2)
+    c = torch.zeros(m, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        least_squares_step(plan, c, ft, lr)
+    torch.cuda.synchronize()
+    losses = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        c, loss = least_squares_step(plan, c, ft, lr)
+        losses.append(loss)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    losses = [float(x) for x in losses]
+    log("gd step %.3f ms, loss %.4g -> %.4g" % (ms, losses[0], losses[-1]))
+    # gradient at the final iterate through autograd
+    cg = c.detach().requires_grad_(True)
+    from paper_2605_21828_amd.autograd import BFApply
+    r = BFApply.apply(cg, plan) - ft
+    (r * r).sum().backward()
+    grad_np = cg.grad.double().cpu().numpy()
+    c_np = c.double().cpu().numpy()
+    reps = 5
+    ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
+    ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)
+    roof = roofline_for("f32", F, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2)
+    base, acc = None, {}
+    if not args.no_cpu_baseline:
+        log("oracle checks: finite differences and dense gradient")
+        sel = {"fd": wl.sample_indices(wid, m, 64, stream=4), "cols": wl.sample_indices(wid, m, 256, stream=3)}
+        base, acc = lsq_checks(fs, pts, c_np, f, grad_np, sel)
+    res = {
+        "metric": "gradient-descent steps/s (FP32 autograd least squares: apply + transposed apply per step)",
+        "value": 1e3 / ms, "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "nrhs": 1, "leaf": w["leaf"], "tol": w["tol"],
+                   "L": int(fs["L"]), "step": "forward apply + autograd backward (transposed apply) + update"},
+        "roofline": roof,
+        "cpu_baseline": base,
+        "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "host_build_seconds": t_build,
+                  "fp32_apply_ms": ms_fwd, "fp32_apply_transpose_ms": ms_bwd, "step_size": lr,
+                  "loss_first": losses[0], "loss_last": losses[-1],
+                  "loss_monotone": all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:])), **acc},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_copy(args):
     """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
     import torch
@@ -343,6 +460,8 @@ def main():
         return bench_batched(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload in ("lsq262144", "lsq131072"):
+        return bench_lsq(args)
     if args.workload == "sphere40962":
         return bench_sphere(args)
 

@@ -30,6 +30,40 @@ def fourier_synthesis_rows(points, modes, rows, c):
     return P @ np.asarray(c, dtype=np.float64)
 
 
+def fourier_synthesis_all(points, modes, c, chunk=16384):
+    """Phi c at every point, for transforms too large to form.
+
+    The sum over modes of c_k s1(k1 x1) s2(k2 x2) is regrouped by distributivity:
+    for each point, sum over the (k1, s1) factors of s1(k1 x1) times the inner
+    sum over the modes sharing that factor, which is one matmul of the x2 factor
+    table with the coefficients laid out on the (k1, s1) x (k2, s2) grid (each
+    mode owns one grid cell).  Nothing else is reordered.
+    """
+    points = np.asarray(points, dtype=np.float64)
+    modes = np.asarray(modes)
+    c = np.asarray(c, dtype=np.float64)
+    vec = c.ndim == 1
+    if vec:
+        c = c[:, None]
+    a = 2 * modes[:, 0] + modes[:, 2]          # index of the x1 factor
+    b = 2 * modes[:, 1] + modes[:, 3]          # index of the x2 factor
+    A, B = int(a.max()) + 1, int(b.max()) + 1
+    out = np.zeros((points.shape[0], c.shape[1]), dtype=np.float64)
+    for s in range(0, points.shape[0], chunk):
+        x1, x2 = points[s:s + chunk, 0], points[s:s + chunk, 1]
+        t1 = np.empty((len(x1), A))
+        t2 = np.empty((len(x2), B))
+        for i in range(A):
+            t1[:, i] = _modes._trig(i % 2, (i // 2) * x1)
+        for i in range(B):
+            t2[:, i] = _modes._trig(i % 2, (i // 2) * x2)
+        for r in range(c.shape[1]):
+            C = np.zeros((A, B))
+            C[a, b] = c[:, r]
+            out[s:s + chunk, r] = np.sum(t1 * (t2 @ C.T), axis=1)
+    return out[:, 0] if vec else out
+
+
 def fourier_analysis_cols(points, modes, cols, f, chunk=8192):
     """(Phi^T f)[cols] for the Fourier transform, streaming over point chunks."""
     points = np.asarray(points)

@@ -61,6 +61,25 @@ class FourierBlocks:
     def shape(self):
         return (self.tab[0].shape[0], self.modes.shape[0])
 
+    def synthesis(self, c, chunk=16384):
+        """Exact Phi c at every point (used to build workload data, e.g. the
+        right-hand side of a least-squares fit).  Each mode's coefficient goes
+        to the cell (x1 factor, x2 factor) of a coefficient grid G; then
+        (Phi c)_j = sum_a tab0[j, a] (tab1 G^T)[j, a]."""
+        c = np.asarray(c, dtype=np.float64)
+        vec = c.ndim == 1
+        if vec:
+            c = c[:, None]
+        A, B = self.tab[0].shape[1], self.tab[1].shape[1]
+        n = self.tab[0].shape[0]
+        out = np.empty((n, c.shape[1]))
+        for r in range(c.shape[1]):
+            G = np.zeros((A, B))
+            G[self.c1, self.c2] = c[:, r]
+            for s in range(0, n, chunk):
+                out[s:s + chunk, r] = np.einsum("ja,ja->j", self.tab[0][s:s + chunk], self.tab[1][s:s + chunk] @ G.T)
+        return out[:, 0] if vec else out
+
     def __call__(self, rows, cols):
         """Phi[rows][:, cols]; rows=None selects every point."""
         cols = np.asarray(cols)

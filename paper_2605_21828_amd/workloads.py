@@ -22,6 +22,9 @@ WORKLOADS = {
     # Differentiable least-squares fit: 262144 iid points, 65536 modes, one RHS.
     "iid262144": dict(wid=5, kind="iid", n=262144, m=65536, leaf=128, tol=1e-8, nrhs=1,
                       precision="f32", coef="decay"),
+    # The same fit at half the linear size (131072 points, 32768 modes).
+    "iid131072": dict(wid=5, kind="iid", n=131072, m=32768, leaf=128, tol=1e-8, nrhs=1,
+                      precision="f32", coef="decay"),
 }
 
 

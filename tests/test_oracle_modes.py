@@ -87,8 +87,32 @@ def test_sampled_rows_and_columns_match_dense():
     assert np.allclose(od.fourier_analysis_cols(pts, md, cols, f, chunk=64), (Phi.T @ f)[cols], rtol=1e-13, atol=1e-11)
 
 
+def test_full_synthesis_regrouping_equals_definition():
+    rng = np.random.default_rng(4)
+    pts = rng.uniform(-np.pi, np.pi, (700, 2))
+    md = om.fourier_modes(300)
+    c = rng.standard_normal((300, 3))
+    ref = om.phi(pts, md) @ c
+    assert np.allclose(od.fourier_synthesis_all(pts, md, c, chunk=128), ref, rtol=1e-12, atol=1e-11)
+    assert np.allclose(od.fourier_synthesis_all(pts, md, c[:, 1]), ref[:, 1], rtol=1e-12, atol=1e-11)
+    # a planted mistake (the sin/cos roles of the x2 factor swapped) is caught
+    bad = md.copy()
+    bad[:, 3] = 1 - bad[:, 3]
+    bad[:, 1] = np.maximum(bad[:, 1], 1)
+    assert not np.allclose(od.fourier_synthesis_all(pts, bad, c), ref, rtol=1e-6, atol=1e-6)
+
+
 def test_rel_err_cols_is_max_over_columns():
     ref = np.array([[1.0, 2.0], [0.0, 0.0]])
     x = np.array([[1.1, 2.0], [0.0, 0.0]])
     mx, fro = od.rel_err_cols(x, ref)
     assert abs(mx - 0.1) < 1e-12 and 0 < fro < 0.1
+
+
+def test_builder_exact_synthesis_matches_definition():
+    from paper_2605_21828_amd.factor.fourier import FourierBlocks, real_modes
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-np.pi, np.pi, (900, 2))
+    c = rng.standard_normal((400, 2))
+    got = FourierBlocks(pts, real_modes(400)).synthesis(c, chunk=100)
+    assert np.allclose(got, om.phi(pts, om.fourier_modes(400)) @ c, rtol=1e-12, atol=1e-11)
