@@ -72,6 +72,10 @@ struct StageArgs {
   int32_t nrhs;
 };
 
+// Zero bytes after the end of every factor pool region: one reduction chunk of
+// any element type (the kernels read whole chunks past a row's end).
+constexpr int kPoolTailBytes = 128;
+
 // Output rows per workgroup tile at one 16-row block per wave; tiles of twice
 // that height (two blocks per wave) are the other shape.  The plan builds tile
 // lists for both heights.

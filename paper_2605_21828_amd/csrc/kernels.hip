@@ -80,11 +80,22 @@ __device__ __forceinline__ int64_t out_row(const StageArgs &a, int32_t base, int
   return a.rowmap ? (int64_t)a.rowmap[base + r] : (int64_t)(base + r);
 }
 
-// Identity block: copy rows [m0, m0 + rows) of the job.
+// Identity block: copy rows [m0, m0 + rows) of the job (16-byte pieces on full-width
+// tiles with 16-byte aligned rows, elements otherwise).
 template <typename T, int BN>
 __device__ __forceinline__ void copy_tile(const StageArgs &a, const FwdJob &J, int m0, int rows, int n0) {
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
+  constexpr int V = 16 / (int)sizeof(T), NV = BN / V;
+  if (a.vec && n0 + BN <= a.nrhs && a.ldd % V == 0 && reinterpret_cast<uintptr_t>(a.dst) % 16 == 0) {
+    for (int e = threadIdx.x; e < rows * NV; e += kNT) {
+      const int r = e / NV, c = (e % NV) * V;
+      const int gr = m0 + r;
+      if (gr < J.M)
+        copy_vec<T, V>(dst + out_row(a, J.out_row, gr) * a.ldd + n0 + c, src + (int64_t)(J.in_row + gr) * a.lds + n0 + c);
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < rows * BN; e += kNT) {
     const int r = e / BN, c = e % BN;
     const int gr = m0 + r, gc = n0 + c;
@@ -110,12 +121,24 @@ struct Tiling {
 // Stage one RHS chunk: rows k0 .. k0+KC of a row-mapped source into registers.
 // Thread t takes row k = t % KC and the XR columns of column group t / KC, so
 // the transposed LDS writes of consecutive lanes hit consecutive addresses.
+// On full-width tiles (`full`, uniform: vector rows and n0 + BN <= nrhs) the load
+// is unconditional from a clamped row and rows past the block are zeroed
+// afterwards, so the loop carries no divergent branches.
 template <typename T, int BN>
 __device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
-                                       int32_t nrows, int k0, int n0, int tid) {
+                                       int32_t nrows, int k0, int n0, int tid, bool full) {
   typedef Tiling<T, BN> Tl;
   const int k = tid % Tl::KC, c = (tid / Tl::KC) * Tl::XR;
   const int gk = k0 + k;
+  if (full) {
+    const int rr = min(gk, nrows - 1);
+    const int64_t srow = rowmap ? (int64_t)rowmap[base + rr] : (int64_t)(base + rr);
+    copy_vec<T, Tl::XR>(xr, static_cast<const T *>(a.src) + srow * a.lds + n0 + c);
+    const bool ok = gk < nrows;
+#pragma unroll
+    for (int i = 0; i < Tl::XR; ++i) xr[i] = ok ? xr[i] : T(0);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < Tl::XR; ++i) xr[i] = T(0);
   if (gk >= nrows) return;
@@ -138,18 +161,15 @@ __device__ __forceinline__ void store_x(T *Xs, const T *xr, int tid) {
   for (int i = 0; i < Tl::XR; ++i) Xs[(c + i) * Tl::XS + k] = xr[i];
 }
 
-// This lane's KL reduction values of factor row `wrow` for the chunk at k0.
-// Row strides are multiples of 8 >= KL, so a lane's values lie in one row.
+// This lane's KL reduction values of factor row `wrow` for the chunk at k0.  A
+// chunk may run past the row's end into the next row, or past the last row into
+// the zero tail every pool carries (at least one chunk long); those values meet
+// right-hand-side rows that load_x zeroed, so they add nothing and the load
+// needs no guard.
 template <typename T, int BN>
-__device__ __forceinline__ void load_w(T *wr, const T *wrow, int ldw, int k0, int lg) {
+__device__ __forceinline__ void load_w(T *wr, const T *wrow, int k0, int lg) {
   typedef Tiling<T, BN> Tl;
-  const int k = k0 + Tl::KL * lg;
-  if (k < ldw) {
-    copy_vec<T, Tl::KL>(wr, wrow + k);
-  } else {
-#pragma unroll
-    for (int i = 0; i < Tl::KL; ++i) wr[i] = T(0);
-  }
+  copy_vec<T, Tl::KL>(wr, wrow + k0 + Tl::KL * lg);
 }
 
 // acc += W_chunk (this wave's FM x 16 rows) * X_chunk (all BN columns).
@@ -173,37 +193,35 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
 
 // Reduction over one factor block: acc += W(rows of this wave) * src rows.
 // W is row-major with stride ldw; the reduction runs over nk source rows read
-// through the optional row map starting at `base`.
+// through the optional row map starting at `base`.  Chunks alternate between two
+// register sets and two LDS buffers (the loop body handles a pair of chunks).
 template <typename T, int BN, int FM>
-__device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int ldw,
-                                           int nk, const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
+__device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int nk,
+                                           const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
                                            T *Xs, int tid, int lrow, int lg, int nact) {
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
+  const bool full = a.vec && n0 + BN <= a.nrhs;
   T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
+  auto load_chunk = [&](T (*w)[Tl::KL], int c) {
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-    if (fm < nact) load_w<T, BN>(wA[fm], wrow[fm], ldw, 0, lg);
-  load_x<T, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
+    for (int fm = 0; fm < FM; ++fm)
+      if (fm < nact) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
+    load_x<T, BN>(xB, a, rowmap, base, nk, c * Tl::KC, n0, tid, full);
+  };
+  load_chunk(wA, 0);
   store_x<T, BN>(Xs, xB, tid);
   __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const bool more = c + 1 < nchunk;
-    if (more) {
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-        if (fm < nact) load_w<T, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
-      load_x<T, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
-    }
-    mma_chunk<T, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
-    if (more) {
-      store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int i = 0; i < Tl::KL; ++i) wA[fm][i] = wB[fm][i];
-    }
+  for (int c = 0; c < nchunk; c += 2) {
+    if (c + 1 < nchunk) load_chunk(wB, c + 1);
+    mma_chunk<T, BN, FM>(acc, wA, Xs, lrow, lg, nact);
+    if (c + 1 < nchunk) store_x<T, BN>(Xs + Tl::XBUF, xB, tid);
+    __syncthreads();
+    if (c + 1 >= nchunk) break;
+    if (c + 2 < nchunk) load_chunk(wA, c + 2);
+    mma_chunk<T, BN, FM>(acc, wB, Xs + Tl::XBUF, lrow, lg, nact);
+    if (c + 2 < nchunk) store_x<T, BN>(Xs, xB, tid);
     __syncthreads();
   }
 }
@@ -233,7 +251,7 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  gemm_block<T, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  gemm_block<T, BN, FM>(acc, wrow, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
   T *dst = static_cast<T *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -274,7 +292,7 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
       wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
-    gemm_block<T, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block<T, BN, FM>(acc, wrow, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
@@ -341,9 +359,21 @@ struct TilingB {
 // into one 32-bit LDS word, so consecutive lanes write consecutive words.
 template <int NTERM, int BN>
 __device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
-                                          int32_t nrows, int k0, int n0, int tid) {
+                                          int32_t nrows, int k0, int n0, int tid, bool full) {
   typedef TilingB<NTERM, BN> Tl;
   const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
+  if (full) {  // unconditional loads from clamped rows, rows past the block zeroed
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gk = k0 + k + h, rr = min(gk, nrows - 1);
+      const int64_t srow = rowmap ? (int64_t)rowmap[base + rr] : (int64_t)(base + rr);
+      copy_vec<float, Tl::XP>(xr + h * Tl::XP, static_cast<const float *>(a.src) + srow * a.lds + n0 + c);
+      const bool ok = gk < nrows;
+#pragma unroll
+      for (int i = 0; i < Tl::XP; ++i) xr[h * Tl::XP + i] = ok ? xr[h * Tl::XP + i] : 0.f;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2 * Tl::XP; ++i) xr[i] = 0.f;
 #pragma unroll
@@ -386,17 +416,16 @@ __device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int ti
 }
 
 // This lane's KL factor values of each term for the chunk at k0 (32 bytes per
-// term).  Row strides are multiples of 8 values, so each 8-value half is either
-// entirely inside the row or entirely past its end.
+// term).  As for load_w, values past the row's end (the next row, or the zero
+// tail of the term pool) meet zeroed right-hand-side rows, so no guard.
 template <int NTERM, int BN>
-__device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const *wrow, int ldw, int k0, int lg) {
+__device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const *wrow, int k0, int lg) {
   typedef TilingB<NTERM, BN> Tl;
   const int k = k0 + Tl::KL * lg;
 #pragma unroll
   for (int t = 0; t < NTERM; ++t)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-      wr[t][h] = k + 8 * h < ldw ? *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h) : make_uint4(0, 0, 0, 0);
+    for (int h = 0; h < 2; ++h) wr[t][h] = *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h);
 }
 
 template <int NTERM, int BN, int FM>
@@ -430,40 +459,35 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
 
 // Reduction over one factor block with split terms.  Xs holds 2 buffers per
 // term: term t buffer j at Xs + (2 t + j) * XBUF.  wrow[fm][t]: term t of row fm.
+// Chunks alternate between two register sets and two LDS buffers.
 template <int NTERM, int BN, int FM>
-__device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int ldw, int nk,
+__device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int nk,
                                               const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
                                               uint16_t *Xs, int tid, int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk == 0) return;
+  const bool full = a.vec && n0 + BN <= a.nrhs;
   uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
+  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-    if (fm < nact) load_w_bf<NTERM, BN>(wA[fm], wrow[fm], ldw, 0, lg);
-  load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, 0, n0, tid);
+    for (int fm = 0; fm < FM; ++fm)
+      if (fm < nact) load_w_bf<NTERM, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
+    load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, c * Tl::KC, n0, tid, full);
+  };
+  load_chunk(wA, 0);
   store_x_bf<NTERM, BN>(Xs, xB, tid);
   __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const bool more = c + 1 < nchunk;
-    if (more) {
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-        if (fm < nact) load_w_bf<NTERM, BN>(wB[fm], wrow[fm], ldw, (c + 1) * Tl::KC, lg);
-      load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, (c + 1) * Tl::KC, n0, tid);
-    }
-    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
-    if (more) {
-      store_x_bf<NTERM, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xB, tid);
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-        for (int t = 0; t < NTERM; ++t) {
-          wA[fm][t][0] = wB[fm][t][0];
-          wA[fm][t][1] = wB[fm][t][1];
-        }
-    }
+  for (int c = 0; c < nchunk; c += 2) {
+    if (c + 1 < nchunk) load_chunk(wB, c + 1);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs, lrow, lg, nact);
+    if (c + 1 < nchunk) store_x_bf<NTERM, BN>(Xs + Tl::XBUF, xB, tid);
+    __syncthreads();
+    if (c + 1 >= nchunk) break;
+    if (c + 2 < nchunk) load_chunk(wA, c + 2);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wB, Xs + Tl::XBUF, lrow, lg, nact);
+    if (c + 2 < nchunk) store_x_bf<NTERM, BN>(Xs, xB, tid);
     __syncthreads();
   }
 }
@@ -496,7 +520,7 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.ldw, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
   float *dst = static_cast<float *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -539,7 +563,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
       wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
       wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.ldwt, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);

@@ -345,15 +345,17 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     p->cols[d].assign(p->stages.size(), 0);
   }
 
-  // Device layout.
+  // Device layout.  Every pool region ends in a zero tail of at least one
+  // reduction chunk (128 bytes for every element type): the kernels read whole
+  // chunks past a row's end without a guard.
   int64_t cur = 0;
   for (int t = 0; t < p->nterms; ++t) {
     p->off_pool[t] = cur;
-    cur = align_up(cur + pool * p->wsz, 256);
+    cur = align_up(cur + pool * p->wsz + kPoolTailBytes, 256);
   }
   for (int t = 0; t < p->nterms; ++t) {
     p->off_tpool[t] = cur;
-    cur = align_up(cur + tpool * p->wsz, 256);
+    cur = align_up(cur + tpool * p->wsz + kPoolTailBytes, 256);
   }
   p->off_fjobs = cur;
   cur = align_up(cur + (int64_t)fj.size() * (int64_t)sizeof(FwdJob), 256);
