@@ -107,8 +107,10 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precisio
 /* Bytes of device memory the plan needs for its factors and tables. */
 int64_t bfmht_plan_device_bytes(const bfmht_plan *plan);
 
-/* Bytes of workspace one apply or apply_transpose with this nrhs needs
- * (two ping-pong level buffers); -1 on a bad argument. */
+/* Bytes of workspace one apply or apply_transpose with this nrhs needs: two
+ * ping-pong level buffers, each large enough for the longest level vector and
+ * for f's n rows (apply_transpose first gathers f into tree order there);
+ * -1 on a bad argument. */
 int64_t bfmht_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
 
 /* Copy the plan's factors and tables into dev_buf (device memory, at least

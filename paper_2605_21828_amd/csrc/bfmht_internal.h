@@ -6,9 +6,10 @@
 //   forward stage 0      : y_0[q]        = P_0j  c[koff[j] ..]          (src = c)
 //   forward stage l=1..L : y_l[q]        = P_lq  y_{l-1}[pair rows]     (level buffers)
 //   forward final stage  : f[perm_x[..]] = U_i   y_L[i]                 (dst = f, row map)
-// The transposed stages run in reverse; a transposed job owns one contiguous
-// run of output rows (the pair of input blocks of a forward level) and sums the
-// transposed products of its consumers, so no two jobs write the same row.
+// The transposed stages run in reverse, after f's rows are gathered into tree
+// order; a transposed job owns one contiguous run of output rows (the pair of
+// input blocks of a forward level) and sums the transposed products of its
+// consumers, so no two jobs write the same row.
 //
 // Factor blocks are stored twice: row-major W (M x K, row stride ldw) for the
 // forward stages and row-major W^T (K x M, row stride ldwt) for the transposed
@@ -68,7 +69,7 @@ struct StageArgs {
   int64_t lds;
   void *dst;
   int64_t ldd;
-  const int32_t *rowmap;  // nullptr when rows are contiguous
+  const int32_t *rowmap;  // output row map of the forward leaf stage (perm_x), else nullptr
   int32_t nrhs;
 };
 
@@ -86,6 +87,10 @@ constexpr int kTileRows = 64;
 // Returns 0 or a hipError_t value.
 int launch_fwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
 int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
+
+// dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).
+int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *perm, int64_t n, void *dst, int64_t ldd,
+                       int nrhs, void *stream);
 
 // One stage of one instance inside a batched launch.
 struct Segment {

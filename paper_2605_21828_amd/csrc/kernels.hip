@@ -20,6 +20,7 @@
 // flight while chunk c runs on the matrix cores, with one barrier per chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "bfmht_internal.h"
@@ -118,39 +119,33 @@ struct Tiling {
   static_assert(XR >= 1 && (kNT / KC) * XR == BN, "staging split: one row per lane, column groups per KC lanes");
 };
 
-// Stage one RHS chunk: rows k0 .. k0+KC of a row-mapped source into registers.
-// Thread t takes row k = t % KC and the XR columns of column group t / KC, so
-// the transposed LDS writes of consecutive lanes hit consecutive addresses.
-// On full-width tiles (`full`, uniform: vector rows and n0 + BN <= nrhs) the load
-// is unconditional from a clamped row and rows past the block are zeroed
-// afterwards, so the loop carries no divergent branches.
-template <typename T, int BN>
-__device__ __forceinline__ void load_x(T *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
-                                       int32_t nrows, int k0, int n0, int tid, bool full) {
+// Stage one RHS chunk: rows k0 .. k0+KC of the source into registers.  Thread t
+// takes row k = t % KC and the XR columns of column group t / KC, so the
+// transposed LDS writes of consecutive lanes hit consecutive addresses.  Rows
+// are clamped and zeroed past the block, columns likewise past nrhs; with FULL
+// (16-byte source rows and every column tile full, fixed per launch) the row
+// segment is one vector load.  No branches: the pipelined loop keeps exact
+// wait counts.
+template <typename T, int BN, bool FULL>
+__device__ __forceinline__ void load_x(T *xr, const StageArgs &a, int32_t base, int32_t nrows, int k0, int n0,
+                                       int tid) {
   typedef Tiling<T, BN> Tl;
   const int k = tid % Tl::KC, c = (tid / Tl::KC) * Tl::XR;
   const int gk = k0 + k;
-  if (full) {
-    const int rr = min(gk, nrows - 1);
-    const int64_t srow = rowmap ? (int64_t)rowmap[base + rr] : (int64_t)(base + rr);
-    copy_vec<T, Tl::XR>(xr, static_cast<const T *>(a.src) + srow * a.lds + n0 + c);
-    const bool ok = gk < nrows;
-#pragma unroll
-    for (int i = 0; i < Tl::XR; ++i) xr[i] = ok ? xr[i] : T(0);
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < Tl::XR; ++i) xr[i] = T(0);
-  if (gk >= nrows) return;
-  const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
-  const T *p = static_cast<const T *>(a.src) + srow * a.lds + n0 + c;
-  if (a.vec && n0 + c + Tl::XR <= a.nrhs) {
-    copy_vec<T, Tl::XR>(xr, p);
+  const T *row = static_cast<const T *>(a.src) + (int64_t)(base + min(gk, nrows - 1)) * a.lds;
+  if constexpr (FULL) {
+    copy_vec<T, Tl::XR>(xr, row + n0 + c);
   } else {
 #pragma unroll
-    for (int i = 0; i < Tl::XR; ++i)
-      if (n0 + c + i < a.nrhs) xr[i] = p[i];
+    for (int i = 0; i < Tl::XR; ++i) {
+      const int gc = n0 + c + i;
+      const T v = row[min(gc, a.nrhs - 1)];
+      xr[i] = gc < a.nrhs ? v : T(0);
+    }
   }
+  const bool ok = gk < nrows;
+#pragma unroll
+  for (int i = 0; i < Tl::XR; ++i) xr[i] = ok ? xr[i] : T(0);
 }
 
 template <typename T, int BN>
@@ -172,62 +167,80 @@ __device__ __forceinline__ void load_w(T *wr, const T *wrow, int k0, int lg) {
   copy_vec<T, Tl::KL>(wr, wrow + k0 + Tl::KL * lg);
 }
 
-// acc += W_chunk (this wave's FM x 16 rows) * X_chunk (all BN columns).
-// Blocks past the job's last row (`nact` active blocks, wave-uniform) are skipped.
+// acc += W_chunk (this wave's FM x 16 rows) * X_chunk (all BN columns).  A wave
+// whose blocks all lie past the job's last row (`nact` = 0, wave-uniform) issues
+// no MFMA.
 template <typename T, int BN, int FM>
 __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16], const T (*wr)[Cfg<T>::KC / 4],
                                           const T *Xs, int lrow, int lg, int nact) {
   typedef Tiling<T, BN> Tl;
+  if (nact <= 0) return;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
     T b[Tl::KL];
     copy_vec<T, Tl::KL>(b, &Xs[(fn * 16 + lrow) * Tl::XS + Tl::KL * lg]);
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-      if (fm < nact) {
+    for (int t = 0; t < Tl::KL; ++t)
 #pragma unroll
-        for (int t = 0; t < Tl::KL; ++t) acc[fm][fn] = mfma16x16x4(wr[fm][t], b[t], acc[fm][fn]);
-      }
+      for (int fm = 0; fm < FM; ++fm) acc[fm][fn] = mfma16x16x4(wr[fm][t], b[t], acc[fm][fn]);
   }
 }
 
-// Reduction over one factor block: acc += W(rows of this wave) * src rows.
-// W is row-major with stride ldw; the reduction runs over nk source rows read
-// through the optional row map starting at `base`.  Chunks alternate between two
-// register sets and two LDS buffers (the loop body handles a pair of chunks).
-template <typename T, int BN, int FM>
+// Reduction over one factor block: acc += W(rows of this wave) * src rows
+// base .. base+nk.  Chunks alternate between two register sets and two LDS
+// buffers; the loads of chunk c+1 are in flight while chunk c runs on the matrix
+// cores.  The loop body has no conditions (the last one or two chunks are peeled
+// off, factor rows are loaded for every block of the wave), so the compiler's
+// wait counts stay exact.  Ends with a barrier, so a following call may restage
+// the buffers.
+template <typename T, int BN, int FM, bool FULL>
 __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int nk,
-                                           const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
-                                           T *Xs, int tid, int lrow, int lg, int nact) {
+                                           const StageArgs &a, int32_t base, int n0, T *Xs, int tid, int lrow,
+                                           int lg, int nact) {
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
-  if (nchunk == 0) return;
-  const bool full = a.vec && n0 + BN <= a.nrhs;
+  if (nchunk <= 0) return;
   T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
+  // RHS first: the wait before staging it into LDS then leaves the factor loads
+  // in flight (loads complete in order).
   auto load_chunk = [&](T (*w)[Tl::KL], int c) {
+    load_x<T, BN, FULL>(xB, a, base, nk, c * Tl::KC, n0, tid);
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-      if (fm < nact) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
-    load_x<T, BN>(xB, a, rowmap, base, nk, c * Tl::KC, n0, tid, full);
+    for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
+  T *X0 = Xs, *X1 = Xs + Tl::XBUF;
   load_chunk(wA, 0);
-  store_x<T, BN>(Xs, xB, tid);
+  store_x<T, BN>(X0, xB, tid);
   __syncthreads();
-  for (int c = 0; c < nchunk; c += 2) {
-    if (c + 1 < nchunk) load_chunk(wB, c + 1);
-    mma_chunk<T, BN, FM>(acc, wA, Xs, lrow, lg, nact);
-    if (c + 1 < nchunk) store_x<T, BN>(Xs + Tl::XBUF, xB, tid);
+  int c = 0;
+  for (; c + 2 < nchunk; c += 2) {
+    load_chunk(wB, c + 1);
+    mma_chunk<T, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    store_x<T, BN>(X1, xB, tid);
     __syncthreads();
-    if (c + 1 >= nchunk) break;
-    if (c + 2 < nchunk) load_chunk(wA, c + 2);
-    mma_chunk<T, BN, FM>(acc, wB, Xs + Tl::XBUF, lrow, lg, nact);
-    if (c + 2 < nchunk) store_x<T, BN>(Xs, xB, tid);
+    load_chunk(wA, c + 2);
+    mma_chunk<T, BN, FM>(acc, wB, X1, lrow, lg, nact);
+    store_x<T, BN>(X0, xB, tid);
     __syncthreads();
   }
+  // one or two chunks left; the last one always runs from wA (one code path)
+  const bool two = c + 1 < nchunk;
+  if (two) {
+    load_chunk(wB, c + 1);
+    mma_chunk<T, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    store_x<T, BN>(X1, xB, tid);
+    __syncthreads();
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int i = 0; i < Tl::KL; ++i) wA[fm][i] = wB[fm][i];
+  }
+  mma_chunk<T, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, nact);
+  __syncthreads();
 }
 
 // Forward stage tile: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
-template <typename T, int BN, int FM>
+template <typename T, int BN, int FM, bool FULL>
 __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
   const Tile tile = a.tiles[tix];
@@ -251,7 +264,7 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  gemm_block<T, BN, FM>(acc, wrow, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  gemm_block<T, BN, FM, FULL>(acc, wrow, J.K, a, J.in_row, n0, Xs, tid, lrow, lg, nact);
   T *dst = static_cast<T *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -267,7 +280,7 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
 
 // Transposed stage tile: dst[out_row .. out_row+K) = sum over consumers of
 // W_c^T g_c, identity consumers adding their gradient rows directly.
-template <typename T, int BN, int FM>
+template <typename T, int BN, int FM, bool FULL>
 __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
   const Tile tile = a.tiles[tix];
@@ -292,7 +305,7 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
       wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
-    gemm_block<T, BN, FM>(acc, wrow, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block<T, BN, FM, FULL>(acc, wrow, C.M, a, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
@@ -310,8 +323,7 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
           for (int ci = 0; ci < 2; ++ci)
             if (ci < J.nc && J.c[ci].wt_off < 0) {
               const int32_t b = J.c[ci].g_row;
-              const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
-              v += src[srow * a.lds + gc];
+              v += src[(int64_t)(b + gr) * a.lds + gc];
             }
           dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
         }
@@ -357,38 +369,28 @@ struct TilingB {
 // transposed.  Thread t takes rows 2 (t % 32) and 2 (t % 32) + 1 and the XP
 // columns of column group t / 32; the two rows' terms of one column are packed
 // into one 32-bit LDS word, so consecutive lanes write consecutive words.
-template <int NTERM, int BN>
-__device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, const int32_t *rowmap, int32_t base,
-                                          int32_t nrows, int k0, int n0, int tid, bool full) {
+template <int NTERM, int BN, bool FULL>
+__device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, int32_t base, int32_t nrows, int k0, int n0,
+                                          int tid) {
   typedef TilingB<NTERM, BN> Tl;
   const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
-  if (full) {  // unconditional loads from clamped rows, rows past the block zeroed
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int gk = k0 + k + h, rr = min(gk, nrows - 1);
-      const int64_t srow = rowmap ? (int64_t)rowmap[base + rr] : (int64_t)(base + rr);
-      copy_vec<float, Tl::XP>(xr + h * Tl::XP, static_cast<const float *>(a.src) + srow * a.lds + n0 + c);
-      const bool ok = gk < nrows;
-#pragma unroll
-      for (int i = 0; i < Tl::XP; ++i) xr[h * Tl::XP + i] = ok ? xr[h * Tl::XP + i] : 0.f;
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < 2 * Tl::XP; ++i) xr[i] = 0.f;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < 2; ++h) {  // clamped rows and columns, zeroed past the block / nrhs (no branches)
     const int gk = k0 + k + h;
-    if (gk >= nrows) continue;
-    const int64_t srow = rowmap ? (int64_t)rowmap[base + gk] : (int64_t)(base + gk);
-    const float *p = static_cast<const float *>(a.src) + srow * a.lds + n0 + c;
-    if (a.vec && n0 + c + Tl::XP <= a.nrhs) {
-      copy_vec<float, Tl::XP>(xr + h * Tl::XP, p);
+    const float *row = static_cast<const float *>(a.src) + (int64_t)(base + min(gk, nrows - 1)) * a.lds;
+    if constexpr (FULL) {
+      copy_vec<float, Tl::XP>(xr + h * Tl::XP, row + n0 + c);
     } else {
 #pragma unroll
-      for (int i = 0; i < Tl::XP; ++i)
-        if (n0 + c + i < a.nrhs) xr[h * Tl::XP + i] = p[i];
+      for (int i = 0; i < Tl::XP; ++i) {
+        const int gc = n0 + c + i;
+        const float v = row[min(gc, a.nrhs - 1)];
+        xr[h * Tl::XP + i] = gc < a.nrhs ? v : 0.f;
+      }
     }
+    const bool ok = gk < nrows;
+#pragma unroll
+    for (int i = 0; i < Tl::XP; ++i) xr[h * Tl::XP + i] = ok ? xr[h * Tl::XP + i] : 0.f;
   }
 }
 
@@ -428,10 +430,12 @@ __device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const 
     for (int h = 0; h < 2; ++h) wr[t][h] = *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h);
 }
 
+// A wave whose blocks all lie past the job's last row (`nact` = 0) issues no MFMA.
 template <int NTERM, int BN, int FM>
 __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*wr)[NTERM][2], const uint16_t *Xs,
                                              int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
+  if (nact <= 0) return;
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
     const int off = (fn * 16 + lrow) * Tl::XS + Tl::KL * lg;
@@ -442,7 +446,6 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
       for (int t = 0; t < NTERM; ++t) b[t] = *reinterpret_cast<const uint4 *>(Xs + t * 2 * Tl::XBUF + off + 8 * h);
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm) {
-        if (fm >= nact) continue;
         // smallest products first
         if constexpr (NTERM == 3) {
           acc[fm][fn] = mfma_bf16(wr[fm][2][h], b[0], acc[fm][fn]);
@@ -457,42 +460,59 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
   }
 }
 
-// Reduction over one factor block with split terms.  Xs holds 2 buffers per
-// term: term t buffer j at Xs + (2 t + j) * XBUF.  wrow[fm][t]: term t of row fm.
-// Chunks alternate between two register sets and two LDS buffers.
-template <int NTERM, int BN, int FM>
+// Pipelined reduction over one factor block with split terms, in the same shape
+// as gemm_block (no conditions in the loop body, tail peeled, final barrier).  Xs
+// holds 2 buffers per term: term t buffer j at Xs + (2 t + j) XBUF.  wrow[fm][t]:
+// term t of row fm.
+template <int NTERM, int BN, int FM, bool FULL>
 __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int nk,
-                                              const StageArgs &a, const int32_t *rowmap, int32_t base, int n0,
-                                              uint16_t *Xs, int tid, int lrow, int lg, int nact) {
+                                              const StageArgs &a, int32_t base, int n0, uint16_t *Xs, int tid,
+                                              int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
-  if (nchunk == 0) return;
-  const bool full = a.vec && n0 + BN <= a.nrhs;
+  if (nchunk <= 0) return;
   uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
-  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {
+  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {  // RHS first, as in gemm_block
+    load_x_bf<NTERM, BN, FULL>(xB, a, base, nk, c * Tl::KC, n0, tid);
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)
-      if (fm < nact) load_w_bf<NTERM, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
-    load_x_bf<NTERM, BN>(xB, a, rowmap, base, nk, c * Tl::KC, n0, tid, full);
+    for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
+  uint16_t *X0 = Xs, *X1 = Xs + Tl::XBUF;
   load_chunk(wA, 0);
-  store_x_bf<NTERM, BN>(Xs, xB, tid);
+  store_x_bf<NTERM, BN>(X0, xB, tid);
   __syncthreads();
-  for (int c = 0; c < nchunk; c += 2) {
-    if (c + 1 < nchunk) load_chunk(wB, c + 1);
-    mma_chunk_bf<NTERM, BN, FM>(acc, wA, Xs, lrow, lg, nact);
-    if (c + 1 < nchunk) store_x_bf<NTERM, BN>(Xs + Tl::XBUF, xB, tid);
+  int c = 0;
+  for (; c + 2 < nchunk; c += 2) {
+    load_chunk(wB, c + 1);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    store_x_bf<NTERM, BN>(X1, xB, tid);
     __syncthreads();
-    if (c + 1 >= nchunk) break;
-    if (c + 2 < nchunk) load_chunk(wA, c + 2);
-    mma_chunk_bf<NTERM, BN, FM>(acc, wB, Xs + Tl::XBUF, lrow, lg, nact);
-    if (c + 2 < nchunk) store_x_bf<NTERM, BN>(Xs, xB, tid);
+    load_chunk(wA, c + 2);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wB, X1, lrow, lg, nact);
+    store_x_bf<NTERM, BN>(X0, xB, tid);
     __syncthreads();
   }
+  // one or two chunks left; the last one always runs from wA (one code path)
+  const bool two = c + 1 < nchunk;
+  if (two) {
+    load_chunk(wB, c + 1);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    store_x_bf<NTERM, BN>(X1, xB, tid);
+    __syncthreads();
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) {
+        wA[fm][t][0] = wB[fm][t][0];
+        wA[fm][t][1] = wB[fm][t][1];
+      }
+  }
+  mma_chunk_bf<NTERM, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, nact);
+  __syncthreads();
 }
 
-template <int NTERM, int BN, int FM>
+template <int NTERM, int BN, int FM, bool FULL>
 __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
   const Tile tile = a.tiles[tix];
@@ -520,7 +540,7 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  gemm_block_bf<NTERM, BN, FM>(acc, wrow, J.K, a, nullptr, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  gemm_block_bf<NTERM, BN, FM, FULL>(acc, wrow, J.K, a, J.in_row, n0, Xs, tid, lrow, lg, nact);
   float *dst = static_cast<float *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -534,7 +554,7 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
       }
 }
 
-template <int NTERM, int BN, int FM>
+template <int NTERM, int BN, int FM, bool FULL>
 __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny, uint16_t *Xs) {
   typedef TilingB<NTERM, BN> Tl;
   const Tile tile = a.tiles[tix];
@@ -563,7 +583,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
       wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
       wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    gemm_block_bf<NTERM, BN, FM>(acc, wrow, C.M, a, a.rowmap, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block_bf<NTERM, BN, FM, FULL>(acc, wrow, C.M, a, C.g_row, n0, Xs, tid, lrow, lg, nact);
   }
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
@@ -581,8 +601,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
           for (int ci = 0; ci < 2; ++ci)
             if (ci < J.nc && J.c[ci].wt_off < 0) {
               const int32_t b = J.c[ci].g_row;
-              const int64_t srow = a.rowmap ? (int64_t)a.rowmap[b + gr] : (int64_t)(b + gr);
-              v += src[srow * a.lds + gc];
+              v += src[(int64_t)(b + gr) * a.lds + gc];
             }
           dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
         }
@@ -598,28 +617,32 @@ template <int BN> struct LdsBytes<P_F32, BN> { static constexpr int bytes = 2 * 
 template <int BN> struct LdsBytes<P_BF16X2, BN> { static constexpr int bytes = 2 * 2 * TilingB<2, BN>::XBUF * 2; };
 template <int BN> struct LdsBytes<P_BF16X3, BN> { static constexpr int bytes = 2 * 3 * TilingB<3, BN>::XBUF * 2; };
 
-template <int P, bool FWD, int BN, int FM>
+template <int P, bool FWD, int BN, int FM, bool FULL>
 __device__ __forceinline__ void run_tile(const StageArgs &a, int tix, int ny, void *lds) {
   if constexpr (P == P_F64 || P == P_F32) {
     typedef typename std::conditional<P == P_F64, double, float>::type T;
-    if constexpr (FWD) fwd_tile<T, BN, FM>(a, tix, ny, static_cast<T *>(lds));
-    else bwd_tile<T, BN, FM>(a, tix, ny, static_cast<T *>(lds));
+    if constexpr (FWD) fwd_tile<T, BN, FM, FULL>(a, tix, ny, static_cast<T *>(lds));
+    else bwd_tile<T, BN, FM, FULL>(a, tix, ny, static_cast<T *>(lds));
   } else {
     constexpr int NTERM = P == P_BF16X2 ? 2 : 3;
-    if constexpr (FWD) fwd_tile_bf<NTERM, BN, FM>(a, tix, ny, static_cast<uint16_t *>(lds));
-    else bwd_tile_bf<NTERM, BN, FM>(a, tix, ny, static_cast<uint16_t *>(lds));
+    if constexpr (FWD) fwd_tile_bf<NTERM, BN, FM, FULL>(a, tix, ny, static_cast<uint16_t *>(lds));
+    else bwd_tile_bf<NTERM, BN, FM, FULL>(a, tix, ny, static_cast<uint16_t *>(lds));
   }
 }
+
+// FULL launches (every column tile full, 16-byte source rows) stage the RHS with
+// vector loads; the others load elements from clamped columns.
+inline bool full_tiles(const StageArgs &a, int bn) { return a.vec && a.nrhs % bn == 0; }
 
 // Workgroup b runs on XCD b % 8.  The tile list interleaves 8 bins (tile
 // 8 s + x belongs to bin x), so block b takes bin x = b % 8 and walks that
 // bin's tiles with the ny column tiles of each tile back to back: the column
 // tiles of one factor tile share its rows through that XCD's L2.
-template <int P, bool FWD, int BN, int FM>
+template <int P, bool FWD, int BN, int FM, bool FULL>
 __global__ __launch_bounds__(kNT) void stage_kernel(StageArgs a, int ny) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, BN>::bytes];
   const int b = blockIdx.x, x = b & 7, s = b >> 3;
-  run_tile<P, FWD, BN, FM>(a, (s / ny) * 8 + x, s % ny, lds);
+  run_tile<P, FWD, BN, FM, FULL>(a, (s / ny) * 8 + x, s % ny, lds);
 }
 
 template <int P, bool FWD, int BN, int FM>
@@ -628,7 +651,10 @@ static int launch_one(const StageArgs &a, void *stream) {
   if (a.ntiles % 8) return (int)hipErrorInvalidValue;  // tile lists come in whole rounds of 8 bins
   const int ny = (a.nrhs + BN - 1) / BN;
   const dim3 grid((unsigned)((int64_t)a.ntiles * ny));
-  hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM>), grid, dim3(kNT), 0, (hipStream_t)stream, a, ny);
+  if (full_tiles(a, BN))
+    hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM, true>), grid, dim3(kNT), 0, (hipStream_t)stream, a, ny);
+  else
+    hipLaunchKernelGGL((stage_kernel<P, FWD, BN, FM, false>), grid, dim3(kNT), 0, (hipStream_t)stream, a, ny);
   return (int)hipGetLastError();
 }
 
@@ -662,6 +688,35 @@ int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *str
 }
 
 // ---------------------------------------------------------------------------
+// Row gather into tree order: dst[t] = src[perm[t]] (rows of nrhs elements).
+// The transposed apply reads its input through this copy, so every stage
+// kernel reads contiguous rows.
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void gather_rows_kernel(const T *src, int64_t lds, const int32_t *perm, int64_t n,
+                                                          T *dst, int64_t ldd, int nrhs) {
+  const int64_t total = n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (int64_t)gridDim.x * kNT) {
+    const int64_t t = e / nrhs, j = e % nrhs;
+    dst[t * ldd + j] = src[(int64_t)perm[t] * lds + j];
+  }
+}
+
+int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *perm, int64_t n, void *dst, int64_t ldd,
+                       int nrhs, void *stream) {
+  const int64_t total = n * nrhs;
+  if (total == 0) return 0;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + kNT - 1) / kNT, 8192);
+  if (esz == 8)
+    hipLaunchKernelGGL((gather_rows_kernel<double>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const double *>(src), lds, perm, n, static_cast<double *>(dst), ldd, nrhs);
+  else
+    hipLaunchKernelGGL((gather_rows_kernel<float>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const float *>(src), lds, perm, n, static_cast<float *>(dst), ldd, nrhs);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Many instances of uneven size per launch.  A batched apply runs one launch
 // per stage position (and per group of kSegsPerLaunch instances): launch k
 // holds the k-th stage of its instances, each workgroup decoding (segment,
@@ -669,14 +724,26 @@ int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *str
 // offsets.  Stages of one instance are ordered by the launch boundaries, so no
 // workgroup ever waits on another.  The segments are launch arguments.
 
-template <int P, bool FWD>
-__device__ __forceinline__ void run_segment(const Segment &S, int tix, int ny, void *lds) {
+template <int P, bool FWD, bool FULL>
+__device__ __forceinline__ void run_segment_w(const Segment &S, int tix, int ny, void *lds) {
   const bool tall = S.fm == 2;
   switch (S.bn) {
-    case 16: if (tall) run_tile<P, FWD, 16, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 16, 1>(S.a, tix, ny, lds); break;
-    case 32: if (tall) run_tile<P, FWD, 32, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 32, 1>(S.a, tix, ny, lds); break;
-    default: if (tall) run_tile<P, FWD, 64, 2>(S.a, tix, ny, lds); else run_tile<P, FWD, 64, 1>(S.a, tix, ny, lds); break;
+    case 16:
+      if (tall) run_tile<P, FWD, 16, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 16, 1, FULL>(S.a, tix, ny, lds);
+      break;
+    case 32:
+      if (tall) run_tile<P, FWD, 32, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 32, 1, FULL>(S.a, tix, ny, lds);
+      break;
+    default:
+      if (tall) run_tile<P, FWD, 64, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 64, 1, FULL>(S.a, tix, ny, lds);
+      break;
   }
+}
+
+template <int P, bool FWD>
+__device__ __forceinline__ void run_segment(const Segment &S, int tix, int ny, void *lds) {
+  if (S.a.vec && S.a.nrhs % S.bn == 0) run_segment_w<P, FWD, true>(S, tix, ny, lds);
+  else run_segment_w<P, FWD, false>(S, tix, ny, lds);
 }
 
 template <int P>
@@ -688,7 +755,7 @@ __global__ __launch_bounds__(kNT) void batched_stage_kernel(SegPack pack) {
     const int32_t mid = (lo + hi + 1) >> 1;
     if (pack.s[mid].item0 <= g) lo = mid; else hi = mid - 1;
   }
-  const Segment &S = pack.s[lo];
+  const Segment S = pack.s[lo];  // by value: the selected segment only
   const int64_t t = g - S.item0;
   const int tix = (int)(t % S.a.ntiles), ny = (int)(t / S.a.ntiles);
   if (S.fwd) run_segment<P, true>(S, tix, ny, lds);

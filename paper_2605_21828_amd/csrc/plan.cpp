@@ -174,6 +174,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     }
     p->max_rows = std::max(p->max_rows, off[lvl][nb]);
   }
+  // A level buffer also holds the transposed apply's input gathered into tree order.
+  p->max_rows = std::max<int64_t>(p->max_rows, f->n);
 
   // Pool offsets of every stored block: W (rows x cols, stride ldw_of(cols)) in
   // the forward pool and W^T (cols x rows, stride ldw_of(rows)) in the
@@ -472,7 +474,8 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h) {
     a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0[h];
     a.ntiles = (int32_t)s.nbtile[h];
   }
-  a.rowmap = s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
+  // the forward leaf stage scatters its rows to the points' order
+  a.rowmap = fwd && s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
   return a;
 }
 
@@ -487,8 +490,10 @@ StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, int rows, 
     if (s.kind == 0) { a.src = in; a.lds = ldin; } else { a.src = buf[(s.level - 1) & 1]; a.lds = nrhs; }
     if (s.kind == 2) { a.dst = out; a.ldd = ldout; } else { a.dst = buf[s.level & 1]; a.ldd = nrhs; }
   } else {
-    // the transposed stage l reads level l (or f) and writes level l-1 (or g)
-    if (s.kind == 2) { a.src = in; a.lds = ldin; } else { a.src = buf[s.level & 1]; a.lds = nrhs; }
+    // the transposed stage l reads level l (the leaf stage: f gathered into tree
+    // order, see gather_input) and writes level l-1 (or g)
+    a.src = buf[s.level & 1];
+    a.lds = nrhs;
     if (s.kind == 0) { a.dst = out; a.ldd = ldout; } else { a.dst = buf[(s.level - 1) & 1]; a.ldd = nrhs; }
   }
   a.vec = vec_ok(a.src, a.lds, p->esz);
@@ -505,11 +510,22 @@ int64_t level_buffer_bytes(const bfmht_plan *p, int32_t nrhs) {
   return align_up(p->max_rows * (int64_t)nrhs * p->esz, 256);
 }
 
+// The transposed apply first gathers f's rows into tree order, into the level
+// buffer its leaf stage reads (the one level L+1 maps to).
+int gather_input(const bfmht_plan *p, const void *in, int64_t ldin, int32_t nrhs, char *const buf[2], void *stream) {
+  return launch_gather_rows((int)p->esz, in, ldin, reinterpret_cast<const int32_t *>(p->dev + p->off_perm), p->n,
+                            buf[(p->L + 1) & 1], nrhs, nrhs, stream);
+}
+
 bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out, int64_t ldout,
                        int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
   bfmht_status st = check_call(p, in, ldin, out, ldout, nrhs, ws, ws_bytes);
   if (st != BFMHT_OK || nrhs == 0) return st;
   char *const buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + level_buffer_bytes(p, nrhs)};
+  if (!fwd) {
+    const int e = gather_input(p, in, ldin, nrhs, buf, stream);
+    if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
+  }
   const int S = (int)p->stages.size();
   for (int k = 0; k < S; ++k) {
     const int si = fwd ? k : S - 1 - k;
@@ -615,6 +631,10 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
     if (ldin[i] < nrhs[i] || ldout[i] < nrhs[i]) return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
     char *base = static_cast<char *>(ws) + L.buf_off[i];
     char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
+    if (!fwd) {
+      const int e = gather_input(p, in[i], ldin[i], nrhs[i], buf, stream);
+      if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
+    }
     const int S = (int)p->stages.size();
     for (int k = 0; k < S; ++k) {
       const int si = fwd ? k : S - 1 - k;
