@@ -192,8 +192,22 @@ def bench_batched(args):
             p.apply(x, out=y)
     ms_seq = event_time(one_by_one, reps, torch)
     rhs_points = sum(p.n * int(x.shape[1]) for p, x in zip(plans, xs))
-    F = sum(fio.stored_entries(built[s]) * b for s, b in inst)
-    achieved = 2.0 * F / (ms_fwd * 1e-3) / 1e12
+    # roofline of the batch: each instance at its own bound (small RHS counts are
+    # HBM-bound, large ones MFMA-bound), summed over the instances
+    t_mfma = t_hbm = t_roof = 0.0
+    for s, b in inst:
+        Fi = fio.stored_entries(built[s])
+        n_i = s * s
+        tm = 2.0 * Fi * b / (MFMA_PEAK["f32"] * 1e12)
+        th = (4.0 * Fi + 4.0 * (n_i + n_i // 4) * b) / (HBM_PEAK * 1e9)
+        t_roof += max(tm, th)
+        if tm >= th:
+            t_mfma += tm
+        else:
+            t_hbm += th
+    frac = t_roof / (ms_fwd * 1e-3)
+    bound = "mfma" if t_mfma >= t_hbm else "hbm"
+    peak = MFMA_PEAK["f32"] if bound == "mfma" else HBM_PEAK
     errs = None
     if not args.no_cpu_baseline:
         from oracle import dense as od
@@ -210,8 +224,12 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched32", "instances": [[s, b] for s, b in inst], "m": "n/4",
                    "leaf": spec["leaf"], "tol": spec["tol"], "step": "batched apply + batched apply_transpose"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": achieved / 157.3, "traffic": None,
+        "roofline": {"bound": bound, "achieved": frac * peak, "peak": peak,
+                     "unit": "TFLOP/s" if bound == "mfma" else "GB/s", "frac": frac, "traffic": None,
+                     "t_roof_ms": t_roof * 1e3, "t_roof_mfma_bound_ms": t_mfma * 1e3,
+                     "t_roof_hbm_bound_ms": t_hbm * 1e3,
+                     "note": "sum over instances of max(HBM time, MFMA time); achieved = frac x peak of the "
+                             "dominant bound",
                      "kernel": "batched_stage_kernel<1> (all launches of one batched FP32 apply)"},
         "cpu_baseline": None,
         "extra": {"batched_apply_ms": ms_fwd, "one_by_one_apply_ms": ms_seq,
@@ -333,14 +351,20 @@ def lsq_checks(fs, pts, c_np, f, grad_np, lam_rows):
     dense = 2.0 * od.fourier_analysis_cols(pts, md_oracle, cols, r)
     dense_err = float(np.linalg.norm(grad_np[cols] - dense) / np.linalg.norm(dense))
     t_dense = time.time() - t1
-    # oracle timing: one butterfly apply + transpose pair at b = 1
+    # oracle timing: apply + transpose pairs at b = 1, about 10 s of host work
     t2 = time.time()
-    ob.apply(fs, c_np[:, None])
-    ob.apply_transpose(fs, f[:, None])
+    passes = 0
+    while passes == 0 or (time.time() - t2 < 10.0 and passes < 32):
+        ob.apply(fs, c_np[:, None])
+        ob.apply_transpose(fs, f[:, None])
+        passes += 1
     t_pair = time.time() - t2
-    base = {"value": 2.0 * int(fs["n"]) / t_pair, "unit": "RHS*points/s", "cores": _blas_threads(), "kind": "oracle",
-            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors, one RHS, %.1f s" % t_pair}
-    return base, {"fd_coordinates": len(coords), "fd_rel_err": fd_err, "fd_seconds": t_fd,
+    base = {"value": 2.0 * int(fs["n"]) * passes / t_pair, "unit": "RHS*points/s", "cores": _blas_threads(),
+            "kind": "oracle",
+            "sample": "oracle butterfly apply + transpose (NumPy FP64) of the same factors, one RHS, %d pass(es), "
+                      "%.1f s" % (passes, t_pair)}
+    return base, {"gradient_check_point": "random N(0,1) coefficients",
+                  "fd_coordinates": len(coords), "fd_rel_err": fd_err, "fd_seconds": t_fd,
                   "dense_cols_sampled": len(cols), "dense_grad_rel_err": dense_err, "dense_seconds": t_dense}
 
 
@@ -392,13 +416,16 @@ def bench_lsq(args):
     ms = (time.perf_counter() - t1) * 1e3 / args.steps
     losses = [float(x) for x in losses]
     log("gd step %.3f ms, loss %.4g -> %.4g" % (ms, losses[0], losses[-1]))
-    # gradient at the final iterate through autograd
-    cg = c.detach().requires_grad_(True)
+    # gradient through autograd at a generic point (random N(0,1) coefficients):
+    # near the minimiser the residual is tiny and FP32 cancellation, not the
+    # transform, would decide the comparison
+    c_chk = torch.tensor(wl.coefficients(wid, m, 1, stream=5)[:, 0], dtype=torch.float32, device=dev)
+    cg = c_chk.detach().requires_grad_(True)
     from paper_2605_21828_amd.autograd import BFApply
     r = BFApply.apply(cg, plan) - ft
     (r * r).sum().backward()
     grad_np = cg.grad.double().cpu().numpy()
-    c_np = c.double().cpu().numpy()
+    c_np = c_chk.double().cpu().numpy()
     reps = 5
     ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
     ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)

@@ -43,12 +43,15 @@ def _init_worker():
 
 
 def _run(tasks, workers):
+    """Yield the ID of every task (in completion order when parallel)."""
     if workers <= 1:
-        return [_id_task(t) for t in tasks]
+        for t in tasks:
+            yield _id_task(t)
+        return
     import multiprocessing as mp
     ctx = mp.get_context("fork")
     with ctx.Pool(workers, initializer=_init_worker) as pool:
-        return list(pool.imap_unordered(_id_task, tasks, chunksize=max(1, len(tasks) // (8 * workers))))
+        yield from pool.imap_unordered(_id_task, tasks, chunksize=max(1, len(tasks) // (8 * workers)))
 
 
 def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=None):
@@ -82,11 +85,15 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
                     cols = np.concatenate([J_prev[q1], J_prev[q1 + 1]])
                     tasks.append((lvl, i * nf + j, a, b, cols))
         J_cur = [None] * nb
-        for _, q, J, P, idf in _run(tasks, workers):
+        t_note = time.time()
+        for done, (_, q, J, P, idf) in enumerate(_run(tasks, workers), 1):
             J_cur[q] = J
             rank[lvl, q] = len(J)
             ident[lvl, q] = 1 if idf else 0
             P_blocks[lvl][q] = P
+            if log and time.time() - t_note > 30.0:   # progress on long levels
+                log(dict(level=lvl, blocks_done=done, blocks=len(tasks), seconds=round(time.time() - t0, 1)))
+                t_note = time.time()
         J_prev = J_cur
         st = dict(level=lvl, seconds=round(time.time() - t0, 3),
                   rank_min=int(rank[lvl].min()), rank_max=int(rank[lvl].max()),
