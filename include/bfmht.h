@@ -134,6 +134,22 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_
                                    int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
                                    void *stream);
 
+/* Scaled synthesis f = Phi~ diag(s) c (Sec. 7.2, Gaussian random fields: the
+ * truncated Karhunen-Loeve expansion, eq. KL-expansion, y = Phi S^(1/2) z is this call with
+ * s = S^(1/2) and c = z).  s: device, m elements, same element type as c.
+ * Otherwise as bfmht_apply; diag(s) c is formed in the workspace, c is left
+ * unchanged.  EINVAL if s is NULL. */
+bfmht_status bfmht_apply_scaled(const bfmht_plan *plan, const void *s, const void *c, int64_t ldc, void *f,
+                                int64_t ldf, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream);
+
+/* Scaled analysis g = diag(s) Phi~^T f.  With s the spectral density S on the
+ * eigenvalues, bfmht_apply(bfmht_apply_transpose_scaled(f)) is the covariance
+ * matrix-vector product Phi S Phi^T f of the truncated kernel expansion
+ * (Sec. 7.2, eq. kernel-representation).  Otherwise as bfmht_apply_transpose.  EINVAL if s is NULL. */
+bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *plan, const void *s, const void *f, int64_t ldf,
+                                          void *g, int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
+                                          void *stream);
+
 /* Number of stages of one apply: L + 2 (level 0, the L transfer levels, the
  * leaf stage), numbered in forward order; -1 for NULL. */
 int32_t bfmht_plan_num_stages(const bfmht_plan *plan);

@@ -87,3 +87,17 @@ def rel_err_cols(x, ref):
     den = np.where(den == 0, 1.0, den)
     fro = np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300)
     return float(np.max(num / den)), float(fro)
+
+
+def covariance(Phi, s):
+    """The truncated kernel matrix Sigma = Phi diag(s) Phi^T (Sec. 7.2, eq.
+    kernel-representation truncated after the columns of Phi)."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    return Phi @ np.diag(np.asarray(s, dtype=np.float64)) @ Phi.T
+
+
+def kl_sample(Phi, s, z):
+    """y = Phi diag(sqrt(s)) z: the truncated Karhunen-Loeve expansion (Sec. 7.2,
+    eq. KL-expansion) for standard normal coefficients z."""
+    return np.asarray(Phi, dtype=np.float64) @ (np.sqrt(np.asarray(s, dtype=np.float64))[:, None] *
+                                                np.asarray(z, dtype=np.float64).reshape(len(s), -1))

@@ -4,7 +4,7 @@ On the periodic square the Laplace-Beltrami eigenfunctions are the complex
 exponentials exp(i k.x) with eigenvalue |k|^2 (Sec. 1, eq. 2D-DFT; Sec. 5,
 opening of the rank analysis).  The transform matrix of the paper has entries
 Phi[j, k] = phi_k(x_j) with the columns ordered by eigenvalue (Sec. 1, eq.
-MHT-sum; Sec. 7.1 orders the modes by k1^2 + k2^2).
+MHT-sum; Sec. 6.1 orders the modes by k1^2 + k2^2).
 
 Reading used here (the paper works with complex modes; the real basis, its
 tie-break and its normalisation are not fixed by the paper):

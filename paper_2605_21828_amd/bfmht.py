@@ -41,6 +41,7 @@ EXPORTED = [
     "bfmht_apply", "bfmht_apply_transpose", "bfmht_plan_destroy", "bfmht_last_error", "bfmht_version",
     "bfmht_plan_num_stages", "bfmht_plan_set_tile", "bfmht_plan_get_tile",
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
+    "bfmht_apply_scaled", "bfmht_apply_transpose_scaled",
 ]
 
 
@@ -61,6 +62,10 @@ def load_library(path=LIB_PATH):
     lib.bfmht_apply.restype = ctypes.c_int
     lib.bfmht_apply_transpose.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp]
     lib.bfmht_apply_transpose.restype = ctypes.c_int
+    lib.bfmht_apply_scaled.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.bfmht_apply_scaled.restype = ctypes.c_int
+    lib.bfmht_apply_transpose_scaled.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.bfmht_apply_transpose_scaled.restype = ctypes.c_int
     lib.bfmht_plan_destroy.argtypes = [vp]
     lib.bfmht_plan_destroy.restype = None
     lib.bfmht_last_error.argtypes = []
@@ -146,6 +151,16 @@ def bfmht_apply(plan, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream=0):
 def bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream=0):
     _check(lib.bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream),
            "bfmht_apply_transpose")
+
+
+def bfmht_apply_scaled(plan, s_ptr, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream=0):
+    _check(lib.bfmht_apply_scaled(plan, s_ptr, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream),
+           "bfmht_apply_scaled")
+
+
+def bfmht_apply_transpose_scaled(plan, s_ptr, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream=0):
+    _check(lib.bfmht_apply_transpose_scaled(plan, s_ptr, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream),
+           "bfmht_apply_transpose_scaled")
 
 
 def bfmht_plan_destroy(plan):
@@ -257,6 +272,41 @@ class Plan:
         stream = torch.cuda.current_stream(self.device).cuda_stream
         bfmht_apply_transpose(self.handle, f.data_ptr(), f.stride(0), g.data_ptr(), g.stride(0), b, ws, wsb, stream)
         return g[:, 0] if squeeze else g
+
+    def _scale(self, s):
+        if s.device != self.device or s.dtype != self.dtype or s.dim() != 1 or s.shape[0] != self.m:
+            raise ValueError("expected a (%d,) %s tensor on %s" % (self.m, self.dtype, self.device))
+        return s.contiguous()
+
+    def apply_scaled(self, s, c, out=None):
+        """f = Phi~ diag(s) c (a Karhunen-Loeve sample when s = sqrt(S) and c ~ N(0, I))."""
+        torch = self.torch
+        s = self._scale(s)
+        c, squeeze = self._prep(c, self.m)
+        b = c.shape[1]
+        f = out if out is not None else torch.empty((self.n, b), dtype=self.dtype, device=self.device)
+        ws, wsb = self.workspace(b)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_apply_scaled(self.handle, s.data_ptr(), c.data_ptr(), c.stride(0), f.data_ptr(), f.stride(0), b, ws,
+                           wsb, stream)
+        return f[:, 0] if squeeze else f
+
+    def apply_t_scaled(self, s, f, out=None):
+        """g = diag(s) Phi~^T f."""
+        torch = self.torch
+        s = self._scale(s)
+        f, squeeze = self._prep(f, self.n)
+        b = f.shape[1]
+        g = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        ws, wsb = self.workspace(b)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_apply_transpose_scaled(self.handle, s.data_ptr(), f.data_ptr(), f.stride(0), g.data_ptr(),
+                                     g.stride(0), b, ws, wsb, stream)
+        return g[:, 0] if squeeze else g
+
+    def covariance_matvec(self, s, v):
+        """Phi~ diag(s) Phi~^T v: the truncated kernel expansion with spectral weights s."""
+        return self.apply(self.apply_t_scaled(s, v))
 
     def __del__(self):
         h = getattr(self, "handle", None)

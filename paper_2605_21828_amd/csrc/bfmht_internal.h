@@ -92,6 +92,10 @@ int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *str
 int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *perm, int64_t n, void *dst, int64_t ldd,
                        int nrhs, void *stream);
 
+// dst[r] = s[r] * src[r] for r < rows (rows of nrhs elements of esz bytes); dst may equal src.
+int launch_scale_rows(int esz, const void *s, const void *src, int64_t lds, int64_t rows, void *dst, int64_t ldd,
+                      int nrhs, void *stream);
+
 // One stage of one instance inside a batched launch.
 struct Segment {
   StageArgs a;

@@ -3,7 +3,7 @@
 // Every stage is a batch of small dense products of uneven size (Sec. 2: the
 // level-0 bases, the transfer blocks of levels 1..L and the leaf column bases
 // are each applied once per vector, which is why storage and apply cost
-// coincide, Sec. 7.2).
+// coincide, Sec. 6.2).
 //
 // Work split.  A workgroup of 4 waves computes a (64 FM)-row x BN-column output
 // tile of one job; each wave owns FM blocks of 16 rows and all BN columns, so
@@ -713,6 +713,35 @@ int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *per
   else
     hipLaunchKernelGGL((gather_rows_kernel<float>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
                        static_cast<const float *>(src), lds, perm, n, static_cast<float *>(dst), ldd, nrhs);
+  return (int)hipGetLastError();
+}
+
+// Row scaling: dst[r] = s[r] * src[r] for r < rows (rows of nrhs elements);
+// dst may equal src (same ld).  Carries the diagonal of the scaled applies.
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void scale_rows_kernel(const T *s, const T *src, int64_t lds, int64_t rows, T *dst,
+                                                         int64_t ldd, int nrhs) {
+  const int64_t total = rows * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (int64_t)gridDim.x * kNT) {
+    const int64_t r = e / nrhs, j = e % nrhs;
+    dst[r * ldd + j] = s[r] * src[r * lds + j];
+  }
+}
+
+int launch_scale_rows(int esz, const void *s, const void *src, int64_t lds, int64_t rows, void *dst, int64_t ldd,
+                      int nrhs, void *stream) {
+  const int64_t total = rows * nrhs;
+  if (total == 0) return 0;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + kNT - 1) / kNT, 8192);
+  if (esz == 8)
+    hipLaunchKernelGGL((scale_rows_kernel<double>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const double *>(s), static_cast<const double *>(src), lds, rows,
+                       static_cast<double *>(dst), ldd, nrhs);
+  else
+    hipLaunchKernelGGL((scale_rows_kernel<float>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const float *>(s), static_cast<const float *>(src), lds, rows,
+                       static_cast<float *>(dst), ldd, nrhs);
   return (int)hipGetLastError();
 }
 

@@ -174,8 +174,9 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     }
     p->max_rows = std::max(p->max_rows, off[lvl][nb]);
   }
-  // A level buffer also holds the transposed apply's input gathered into tree order.
-  p->max_rows = std::max<int64_t>(p->max_rows, f->n);
+  // A level buffer also holds the transposed apply's input gathered into tree
+  // order (n rows) and the scaled apply's scaled coefficients (m rows).
+  p->max_rows = std::max<int64_t>(p->max_rows, std::max<int64_t>(f->n, f->m));
 
   // Pool offsets of every stored block: W (rows x cols, stride ldw_of(cols)) in
   // the forward pool and W^T (cols x rows, stride ldw_of(rows)) in the
@@ -547,6 +548,29 @@ extern "C" {
 bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *f, int64_t ldf, int32_t nrhs,
                          void *ws, int64_t ws_bytes, void *stream) {
   return run_apply(p, true, c, ldc, f, ldf, nrhs, ws, ws_bytes, stream);
+}
+
+bfmht_status bfmht_apply_scaled(const bfmht_plan *p, const void *s, const void *c, int64_t ldc, void *f, int64_t ldf,
+                                int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
+  bfmht_status st = check_call(p, c, ldc, f, ldf, nrhs, ws, ws_bytes);
+  if (st != BFMHT_OK || nrhs == 0) return st;
+  if (!s) return fail(BFMHT_EINVAL, "scale vector is NULL");
+  // diag(s) c goes to the second level buffer, which stage 0 does not write and
+  // stage 1 overwrites only after stage 0 has read it
+  char *scaled = static_cast<char *>(ws) + level_buffer_bytes(p, nrhs);
+  const int e = launch_scale_rows((int)p->esz, s, c, ldc, p->m, scaled, nrhs, nrhs, stream);
+  if (e) return fail(BFMHT_EHIP, std::string("scale launch: ") + hipGetErrorString((hipError_t)e));
+  return run_apply(p, true, scaled, nrhs, f, ldf, nrhs, ws, ws_bytes, stream);
+}
+
+bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *p, const void *s, const void *f, int64_t ldf, void *g,
+                                          int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
+  if (nrhs > 0 && !s) return fail(BFMHT_EINVAL, "scale vector is NULL");
+  bfmht_status st = run_apply(p, false, f, ldf, g, ldg, nrhs, ws, ws_bytes, stream);
+  if (st != BFMHT_OK || nrhs == 0) return st;
+  const int e = launch_scale_rows((int)p->esz, s, g, ldg, p->m, g, ldg, nrhs, stream);
+  if (e) return fail(BFMHT_EHIP, std::string("scale launch: ") + hipGetErrorString((hipError_t)e));
+  return BFMHT_OK;
 }
 
 bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t ldf, void *g, int64_t ldg,

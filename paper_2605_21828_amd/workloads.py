@@ -7,7 +7,7 @@ coordinates, 5 = anything else.
 
 The paper's own meshes and datasets are not available; these workloads stand
 in for them with the sizes and structure of its experiments on the flat
-periodic square (Sec. 7.1: uniform and nonuniform points on [-pi, pi]^2, modes
+periodic square (Sec. 6.1: uniform and nonuniform points on [-pi, pi]^2, modes
 ordered by eigenvalue).
 """
 import numpy as np

@@ -4,7 +4,7 @@ O2 is pinned by: (1) exactness at tolerance 0, where the factor set reproduces
 Phi and O2 must equal the dense product; (2) the independent sparse-product
 formulation (Sec. 2, Remark on the sparse-factor view) on random factor sets
 with uneven ranks, identity blocks and empty leaves; (3) the adjoint identity;
-(4) the error tracking the ID tolerance (Sec. 7.1, the matvec error follows
+(4) the error tracking the ID tolerance (Sec. 6.1, the matvec error follows
 the requested tolerance).  Mutation tests plant plausible mistakes in the
 oracle and show that a pin fails.
 """
