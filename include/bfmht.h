@@ -150,6 +150,23 @@ bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *plan, const void *s,
                                           void *g, int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
                                           void *stream);
 
+/* Inverse transform by least squares (Sec. 7.1, eq. inverse-MHT): for every
+ * column of f, `iters` steps of LSQR (Paige and Saunders' Golub-Kahan
+ * bidiagonalization with plane rotations) on min ||Phi~ x - f||_2, each step
+ * one bfmht_apply and one bfmht_apply_transpose plus vector kernels; the whole
+ * solve is enqueued on `stream` with no host synchronization.
+ * f: device n x nrhs (ld ldf), read only; x: device m x nrhs (ld ldx), the
+ * iterate after `iters` steps (zero for iters = 0); rnorm: device nrhs
+ * elements (or NULL), LSQR's estimate of ||Phi~ x - f||_2 per column after the
+ * last step.  Element type as bfmht_apply.  ws: device workspace of at least
+ * bfmht_lsqr_workspace_bytes(plan, nrhs) bytes, 256-byte aligned, not
+ * overlapping f, x or rnorm.  EINVAL on bad arguments or iters < 0, ESTATE if
+ * not uploaded, ENOSPACE if ws is too small.  A column whose residual or
+ * projected residual vanishes keeps its iterate from then on. */
+bfmht_status bfmht_lsqr(const bfmht_plan *plan, const void *f, int64_t ldf, void *x, int64_t ldx, int32_t nrhs,
+                        int32_t iters, void *rnorm, void *ws, int64_t ws_bytes, void *stream);
+int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
+
 /* Number of stages of one apply: L + 2 (level 0, the L transfer levels, the
  * leaf stage), numbered in forward order; -1 for NULL. */
 int32_t bfmht_plan_num_stages(const bfmht_plan *plan);

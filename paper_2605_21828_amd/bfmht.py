@@ -41,7 +41,7 @@ EXPORTED = [
     "bfmht_apply", "bfmht_apply_transpose", "bfmht_plan_destroy", "bfmht_last_error", "bfmht_version",
     "bfmht_plan_num_stages", "bfmht_plan_set_tile", "bfmht_plan_get_tile",
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
-    "bfmht_apply_scaled", "bfmht_apply_transpose_scaled",
+    "bfmht_apply_scaled", "bfmht_apply_transpose_scaled", "bfmht_lsqr", "bfmht_lsqr_workspace_bytes",
 ]
 
 
@@ -66,6 +66,10 @@ def load_library(path=LIB_PATH):
     lib.bfmht_apply_scaled.restype = ctypes.c_int
     lib.bfmht_apply_transpose_scaled.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
     lib.bfmht_apply_transpose_scaled.restype = ctypes.c_int
+    lib.bfmht_lsqr.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp, vp, i64, vp]
+    lib.bfmht_lsqr.restype = ctypes.c_int
+    lib.bfmht_lsqr_workspace_bytes.argtypes = [vp, i32]
+    lib.bfmht_lsqr_workspace_bytes.restype = i64
     lib.bfmht_plan_destroy.argtypes = [vp]
     lib.bfmht_plan_destroy.restype = None
     lib.bfmht_last_error.argtypes = []
@@ -161,6 +165,15 @@ def bfmht_apply_scaled(plan, s_ptr, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_byt
 def bfmht_apply_transpose_scaled(plan, s_ptr, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream=0):
     _check(lib.bfmht_apply_transpose_scaled(plan, s_ptr, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream),
            "bfmht_apply_transpose_scaled")
+
+
+def bfmht_lsqr(plan, f_ptr, ldf, x_ptr, ldx, nrhs, iters, rnorm_ptr, ws_ptr, ws_bytes, stream=0):
+    _check(lib.bfmht_lsqr(plan, f_ptr, ldf, x_ptr, ldx, nrhs, iters, rnorm_ptr, ws_ptr, ws_bytes, stream),
+           "bfmht_lsqr")
+
+
+def bfmht_lsqr_workspace_bytes(plan, nrhs):
+    return lib.bfmht_lsqr_workspace_bytes(plan, int(nrhs))
 
 
 def bfmht_plan_destroy(plan):
@@ -303,6 +316,23 @@ class Plan:
         bfmht_apply_transpose_scaled(self.handle, s.data_ptr(), f.data_ptr(), f.stride(0), g.data_ptr(),
                                      g.stride(0), b, ws, wsb, stream)
         return g[:, 0] if squeeze else g
+
+    def lsqr(self, f, iters, out=None):
+        """Least squares min ||Phi~ x - f|| per column by `iters` LSQR steps on the GPU
+        (the inverse transform); returns (x, rnorm estimate per column)."""
+        torch = self.torch
+        f, squeeze = self._prep(f, self.n)
+        b = f.shape[1]
+        x = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        rnorm = torch.empty(b, dtype=self.dtype, device=self.device)
+        need = bfmht_lsqr_workspace_bytes(self.handle, b)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        bfmht_lsqr(self.handle, f.data_ptr(), f.stride(0), x.data_ptr(), x.stride(0), b, int(iters),
+                   rnorm.data_ptr(), ws_ptr, need, stream)
+        self._lsqr_ws = ws   # kept alive until the enqueued solve has run
+        return (x[:, 0] if squeeze else x), rnorm
 
     def covariance_matvec(self, s, v):
         """Phi~ diag(s) Phi~^T v: the truncated kernel expansion with spectral weights s."""

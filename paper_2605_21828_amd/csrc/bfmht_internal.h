@@ -96,6 +96,22 @@ int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *per
 int launch_scale_rows(int esz, const void *s, const void *src, int64_t lds, int64_t rows, void *dst, int64_t ldd,
                       int nrhs, void *stream);
 
+// LSQR vector kernels (lsqr.hip).  esz: 8 for double, 4 for float; every vector
+// rows x b with ld = b unless a leading dimension is passed; scalars arrays of b.
+constexpr int kLsqrMaxBlocks = 512;   // partial-sum rows of a column norm
+int lsqr_norm_blocks(int64_t rows);
+// u = y - coef u (u = y when coef is null); norm = column 2-norms of u; u *= 1 / norm.
+int lsqr_normalize(int esz, const void *y, int64_t ldy, int64_t rows, int b, const void *coef, void *u,
+                   void *partial, void *norm, void *inv, void *stream);
+// one plane rotation per column (rhobar, phibar advance; cx, cw, rnorm written)
+int lsqr_rotate(int esz, int b, const void *alpha, const void *beta, void *rhobar, void *phibar, void *cx, void *cw,
+                void *rnorm, void *stream);
+// x += cx w; w = v - cw w
+int lsqr_update(int esz, void *x, int64_t ldx, void *w, const void *v, int64_t rows, int b, const void *cx,
+                const void *cw, void *stream);
+// x = 0; w = v
+int lsqr_init(int esz, void *x, int64_t ldx, void *w, const void *v, int64_t rows, int b, void *stream);
+
 // One stage of one instance inside a batched launch.
 struct Segment {
   StageArgs a;

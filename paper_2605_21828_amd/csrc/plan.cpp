@@ -578,6 +578,79 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t l
   return run_apply(p, false, f, ldf, g, ldg, nrhs, ws, ws_bytes, stream);
 }
 
+// LSQR workspace: the apply workspace, then u, y (n x b), v, z, w (m x b), the
+// norm partial sums and eight scalar arrays, each region 256-byte aligned.
+namespace {
+struct LsqrLayout {
+  int64_t apply_ws, u, y, v, z, w, partial, scal, total;
+};
+LsqrLayout lsqr_layout(const bfmht_plan *p, int32_t nrhs) {
+  LsqrLayout L{};
+  const int64_t e = p->esz, b = nrhs;
+  int64_t cur = 0;
+  auto take = [&](int64_t bytes) { const int64_t at = cur; cur = align_up(cur + bytes, 256); return at; };
+  L.apply_ws = take(bfmht_workspace_bytes(p, nrhs));
+  L.u = take(p->n * b * e);
+  L.y = take(p->n * b * e);
+  L.v = take(p->m * b * e);
+  L.z = take(p->m * b * e);
+  L.w = take(p->m * b * e);
+  L.partial = take((int64_t)kLsqrMaxBlocks * b * e);
+  L.scal = take(8 * b * e);
+  L.total = std::max<int64_t>(cur, 256);
+  return L;
+}
+}  // namespace
+
+int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *p, int32_t nrhs) {
+  if (!p || nrhs < 0) return -1;
+  return lsqr_layout(p, nrhs).total;
+}
+
+bfmht_status bfmht_lsqr(const bfmht_plan *p, const void *f, int64_t ldf, void *x, int64_t ldx, int32_t nrhs,
+                        int32_t iters, void *rnorm, void *ws, int64_t ws_bytes, void *stream) {
+  if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
+  if (!p->uploaded) return fail(BFMHT_ESTATE, "plan not uploaded");
+  if (nrhs < 0 || iters < 0) return fail(BFMHT_EINVAL, "nrhs or iters < 0");
+  if (nrhs == 0) return BFMHT_OK;
+  if (!f || !x || !ws) return fail(BFMHT_EINVAL, "NULL right-hand side, solution or workspace");
+  if (ldf < nrhs || ldx < nrhs) return fail(BFMHT_EINVAL, "ld smaller than nrhs");
+  if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
+  const LsqrLayout L = lsqr_layout(p, nrhs);
+  if (ws_bytes < L.total) return fail(BFMHT_ENOSPACE, "workspace too small for LSQR");
+  char *W = static_cast<char *>(ws);
+  void *aws = W + L.apply_ws;
+  const int64_t aws_bytes = bfmht_workspace_bytes(p, nrhs);
+  char *u = W + L.u, *y = W + L.y, *v = W + L.v, *z = W + L.z, *w = W + L.w, *partial = W + L.partial;
+  const int64_t e = p->esz, b = nrhs;
+  char *alpha = W + L.scal, *beta = alpha + b * e, *rhobar = beta + b * e, *phibar = rhobar + b * e;
+  char *cx = phibar + b * e, *cw = cx + b * e, *inv = cw + b * e;
+  const int es = (int)e;
+  auto ok = [&](int rc, const char *what) -> bfmht_status {
+    return rc ? fail(BFMHT_EHIP, std::string(what) + ": " + hipGetErrorString((hipError_t)rc)) : BFMHT_OK;
+  };
+  bfmht_status st;
+  // beta_1 u_1 = f (beta_1 into phibar); alpha_1 v_1 = Phi~^T u_1; rhobar_1 = alpha_1; w_1 = v_1; x_0 = 0
+  if ((st = ok(lsqr_normalize(es, f, ldf, p->n, nrhs, nullptr, u, partial, phibar, inv, stream), "LSQR start"))) return st;
+  if ((st = run_apply(p, false, u, b, z, b, nrhs, aws, aws_bytes, stream))) return st;
+  if ((st = ok(lsqr_normalize(es, z, b, p->m, nrhs, nullptr, v, partial, alpha, inv, stream), "LSQR start"))) return st;
+  if ((st = ok((int)hipMemcpyAsync(rhobar, alpha, b * e, hipMemcpyDeviceToDevice, (hipStream_t)stream), "LSQR start")))
+    return st;
+  if ((st = ok(lsqr_init(es, x, ldx, w, v, p->m, nrhs, stream), "LSQR start"))) return st;
+  for (int32_t it = 0; it < iters; ++it) {
+    // beta_{i+1} u_{i+1} = Phi~ v_i - alpha_i u_i
+    if ((st = run_apply(p, true, v, b, y, b, nrhs, aws, aws_bytes, stream))) return st;
+    if ((st = ok(lsqr_normalize(es, y, b, p->n, nrhs, alpha, u, partial, beta, inv, stream), "LSQR u"))) return st;
+    // alpha_{i+1} v_{i+1} = Phi~^T u_{i+1} - beta_{i+1} v_i
+    if ((st = run_apply(p, false, u, b, z, b, nrhs, aws, aws_bytes, stream))) return st;
+    if ((st = ok(lsqr_normalize(es, z, b, p->m, nrhs, beta, v, partial, alpha, inv, stream), "LSQR v"))) return st;
+    if ((st = ok(lsqr_rotate(es, nrhs, alpha, beta, rhobar, phibar, cx, cw, rnorm, stream), "LSQR rotation")))
+      return st;
+    if ((st = ok(lsqr_update(es, x, ldx, w, v, p->m, nrhs, cx, cw, stream), "LSQR update"))) return st;
+  }
+  return BFMHT_OK;
+}
+
 int32_t bfmht_plan_num_stages(const bfmht_plan *p) { return p ? (int32_t)p->stages.size() : -1; }
 
 bfmht_status bfmht_plan_set_tile(bfmht_plan *p, int32_t transpose, int32_t stage, int32_t rows, int32_t cols) {
