@@ -452,6 +452,72 @@ def bench_lsq(args):
     print(json.dumps(res), flush=True)
 
 
+def lsqr_checks(Phi, X, c):
+    """Oracle leg of the inverse-transform workload: dense FP64 least squares of
+    the same coordinates (and its time on the host cores)."""
+    t0 = time.time()
+    ref = np.linalg.lstsq(Phi, X, rcond=None)[0]
+    dt = time.time() - t0
+    from oracle import dense as od
+    base = {"value": 1.0 / dt, "unit": "solves/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": "dense FP64 least squares (numpy lstsq) of the %d coordinate columns, %.1f s" % (X.shape[1], dt)}
+    return base, {"coef_rel_err_vs_dense_lstsq": od.rel_err_cols(c, ref)[0]}
+
+
+def bench_inverse(args):
+    """Inverse transform of the perturbed sphere's vertex coordinates by LSQR (Sec. 7.1)."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+
+    spec = wl.SPHERE
+    prec = args.precision or "f32"
+    log("building sphere problem and factors: level %d, m=%d" % (spec["level"], spec["m"]))
+    fs, prob = fio.sphere_factors(spec["level"], spec["wid"], spec["m"], spec["leaf"], spec["tol"],
+                                  workers=args.workers, log=lambda s: log("  ", s), cache=args.cache)
+    X = np.asarray(prob["v"], dtype=np.float64)
+    n, m, b = X.shape[0], spec["m"], X.shape[1]
+    F = fio.stored_entries(fs)
+    dev = torch.device("cuda:0")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    p = Plan(fs, prec, max_nrhs=b, device=dev)
+    Xt = torch.tensor(X, dtype=dt, device=dev)
+    iters = args.steps
+    for _ in range(max(1, args.warmup)):
+        p.lsqr(Xt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, rn = p.lsqr(Xt, iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    per_iter = ms / max(1, iters)
+    c_np = c.double().cpu().numpy()
+    # algorithmic bytes of one step: both applies' factor bytes plus their inputs and outputs
+    launches = 2 * (int(fs["L"]) + 2)
+    step_bytes = 2 * (FACTOR_BYTES[prec] * F + (8 if prec == "f64" else 4) * (n + m) * b)
+    achieved = step_bytes / (per_iter * 1e-3) / 1e9
+    base, acc = (None, {})
+    if not args.no_cpu_baseline:
+        base, acc = lsqr_checks(prob["Phi"], X, c_np)
+    res = {
+        "metric": "LSQR steps/s (inverse transform of the vertex coordinates, %s)" % prec,
+        "value": 1e3 / per_iter, "unit": "steps/s",
+        "n_gpus": 1, "steps": iters, "warmup": args.warmup, "ms_per_step": per_iter,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "inverse_sphere40962", "n": n, "m": m, "nrhs": b, "leaf": spec["leaf"],
+                   "tol": spec["tol"], "L": int(fs["L"]), "step": "one LSQR step: apply + apply_transpose + vector kernels"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None, "avg_launch_ms": per_iter / launches,
+                     "per_step_alg_bytes": step_bytes},
+        "cpu_baseline": base,
+        "extra": {"stored_factor_entries": F, "lsqr_steps": iters, "solve_ms": ms,
+                  "residual_estimate": rn.double().cpu().numpy().tolist(), **acc},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_copy(args):
     """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
     import torch
@@ -487,6 +553,8 @@ def main():
         return bench_batched(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "inverse_sphere40962":
+        return bench_inverse(args)
     if args.workload in ("lsq262144", "lsq131072"):
         return bench_lsq(args)
     if args.workload == "sphere40962":
