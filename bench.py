@@ -61,7 +61,9 @@ def roofline_for(prec, F, n, m, b, apply_ms, launches):
     """Roofline of one apply: the binding one of the MFMA time (executed flops,
     split products counted, at the type's peak) and the HBM time (algorithmic
     bytes: stored factors plus inputs and outputs).  `achieved` is that
-    quantity per launch over the average launch duration."""
+    quantity per launch over the average launch duration.  F is the number of
+    factor entries the timed apply reads (the forward pool keeps only T of the
+    compact ID blocks)."""
     io = (8 if prec == "f64" else 4) * (n + m) * b
     alg_bytes = FACTOR_BYTES[prec] * F + io
     exec_flops = 2.0 * F * b * SPLIT_PRODUCTS[prec]
@@ -196,7 +198,7 @@ def bench_batched(args):
     # HBM-bound, large ones MFMA-bound), summed over the instances
     t_mfma = t_hbm = t_roof = 0.0
     for s, b in inst:
-        Fi = fio.stored_entries(built[s])
+        Fi = by_side[s].stored_fwd   # forward pool entries (compact ID blocks)
         n_i = s * s
         tm = 2.0 * Fi * b / (MFMA_PEAK["f32"] * 1e12)
         th = (4.0 * Fi + 4.0 * (n_i + n_i // 4) * b) / (HBM_PEAK * 1e9)
@@ -286,7 +288,8 @@ def bench_sphere(args):
         t_f = event_time(lambda: p.apply(ct, out=y), reps, torch)
         t_b = event_time(lambda: p.apply_t(ft, out=g), reps, torch)
         outs[prec] = (y.double().cpu().numpy(), g.double().cpu().numpy())
-        rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b, "tile_shapes": shapes}
+        rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b, "tile_shapes": shapes,
+                     "forward_factor_entries": p.stored_fwd}
         log("%s step %.3f ms" % (prec, ms))
         del p, ct, ft, y, g
         torch.cuda.empty_cache()
@@ -311,7 +314,7 @@ def bench_sphere(args):
     else:
         base = None
     t_main = rec[main]["apply_ms"]
-    roof = roofline_for(main, F, n, m, b, t_main, launches=int(fs["L"]) + 2)
+    roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=int(fs["L"]) + 2)
     res = {
         "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
         "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
@@ -429,7 +432,7 @@ def bench_lsq(args):
     reps = 5
     ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
     ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)
-    roof = roofline_for("f32", F, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2)
+    roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2)
     base, acc = None, {}
     if not args.no_cpu_baseline:
         log("oracle checks: finite differences and dense gradient")
@@ -494,9 +497,11 @@ def bench_inverse(args):
     ms = (time.perf_counter() - t0) * 1e3
     per_iter = ms / max(1, iters)
     c_np = c.double().cpu().numpy()
-    # algorithmic bytes of one step: both applies' factor bytes plus their inputs and outputs
+    # algorithmic bytes of one step: both applies' factor bytes (the forward one
+    # reads the compact ID blocks) plus their inputs and outputs
     launches = 2 * (int(fs["L"]) + 2)
-    step_bytes = 2 * (FACTOR_BYTES[prec] * F + (8 if prec == "f64" else 4) * (n + m) * b)
+    step_bytes = (FACTOR_BYTES[prec] * (p.stored_fwd + p.stored_t)
+                  + 2 * (8 if prec == "f64" else 4) * (n + m) * b)
     achieved = step_bytes / (per_iter * 1e-3) / 1e9
     base, acc = (None, {})
     if not args.no_cpu_baseline:
@@ -611,13 +616,17 @@ def main():
     ms_fwd = event_time(lambda: p32.apply(c32, out=y32), reps, torch)
     ms_bwd = event_time(lambda: p32.apply_t(f32, out=g32), reps, torch)
     launches = int(fs["L"]) + 2   # stage-0, L transfer levels, final stage
-    flops = 2.0 * F * b
-    alg_bytes32 = 4.0 * F + 4.0 * (n + m) * b
+    # the forward apply reads the compact ID blocks (T only): its algorithmic
+    # factor entries are the forward pool's, not the full factor count F
+    F_fwd = p32.stored_fwd
+    flops = 2.0 * F_fwd * b
+    alg_bytes32 = 4.0 * F_fwd + 4.0 * (n + m) * b
     achieved = flops / (ms_fwd * 1e-3) / 1e12
     result_extra = {
         "fp32_apply_ms": ms_fwd, "fp32_apply_transpose_ms": ms_bwd,
         "fp32_apply_alg_GBps": alg_bytes32 / (ms_fwd * 1e-3) / 1e9,
         "stored_factor_entries": F, "compression_vs_dense": n * m / F,
+        "forward_factor_entries": F_fwd,
         "stage_launches_per_apply": launches,
         "tile_shapes": tuned,
     }
@@ -648,7 +657,7 @@ def main():
         rec = {"apply_ms": t_f, "apply_transpose_ms": t_b,
                "speedup_vs_fp32": (ms_fwd + ms_bwd) / (t_f + t_b),
                "plan_device_GB": pv.device_bytes / 1e9, "tile_shapes": shapes,
-               "roofline": roofline_for(prec, F, n, m, b, t_f, launches)}
+               "roofline": roofline_for(prec, pv.stored_fwd, n, m, b, t_f, launches)}
         if prec == "f64":
             y64 = yv.clone()
         else:

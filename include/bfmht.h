@@ -104,6 +104,25 @@ typedef struct {
 bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precision prec,
                                int32_t max_nrhs, bfmht_plan **plan);
 
+/* Plan flags of bfmht_plan_create_ex. */
+#define BFMHT_PLAN_FULL_BLOCKS 1 /* store every ID block as the full P (no compact form) */
+
+/* bfmht_plan_create with flags (0 = the default of bfmht_plan_create).  By
+ * default a transfer or level-0 block whose P has the column-ID structure
+ * P = [I T] Pi^T (Sec. 2: the skeleton columns of an interpolative
+ * decomposition, each exactly a unit vector) is applied in compact form in the
+ * forward direction: only T is stored and the skeleton rows are added, which
+ * saves the identity part's bytes and flops; results agree with the full form
+ * up to rounding.  BFMHT_PLAN_FULL_BLOCKS keeps the full P.  EINVAL on unknown
+ * flags; otherwise as bfmht_plan_create. */
+bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *factors, bfmht_precision prec, int32_t max_nrhs,
+                                  int32_t flags, bfmht_plan **plan);
+
+/* Factor entries one apply reads: transpose = 0 for the forward direction
+ * (compact blocks count T only), 1 for the transposed direction (every block
+ * in full); -1 if plan is NULL. */
+int64_t bfmht_plan_stored_entries(const bfmht_plan *plan, int32_t transpose);
+
 /* Bytes of device memory the plan needs for its factors and tables. */
 int64_t bfmht_plan_device_bytes(const bfmht_plan *plan);
 

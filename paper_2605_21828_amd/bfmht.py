@@ -42,7 +42,10 @@ EXPORTED = [
     "bfmht_plan_num_stages", "bfmht_plan_set_tile", "bfmht_plan_get_tile",
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
     "bfmht_apply_scaled", "bfmht_apply_transpose_scaled", "bfmht_lsqr", "bfmht_lsqr_workspace_bytes",
+    "bfmht_plan_create_ex", "bfmht_plan_stored_entries",
 ]
+
+PLAN_FULL_BLOCKS = 1  # plan flag: keep every ID block as the full P (no compact forward form)
 
 
 def load_library(path=LIB_PATH):
@@ -52,6 +55,11 @@ def load_library(path=LIB_PATH):
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.bfmht_plan_create.argtypes = [ctypes.POINTER(bfmht_factors_host), ctypes.c_int, i32, ctypes.POINTER(vp)]
     lib.bfmht_plan_create.restype = ctypes.c_int
+    lib.bfmht_plan_create_ex.argtypes = [ctypes.POINTER(bfmht_factors_host), ctypes.c_int, i32, i32,
+                                         ctypes.POINTER(vp)]
+    lib.bfmht_plan_create_ex.restype = ctypes.c_int
+    lib.bfmht_plan_stored_entries.argtypes = [vp, i32]
+    lib.bfmht_plan_stored_entries.restype = i64
     lib.bfmht_plan_device_bytes.argtypes = [vp]
     lib.bfmht_plan_device_bytes.restype = i64
     lib.bfmht_workspace_bytes.argtypes = [vp, i32]
@@ -136,6 +144,20 @@ def bfmht_plan_create(fs, precision, max_nrhs=1):
     return h.value
 
 
+def bfmht_plan_create_ex(fs, precision, max_nrhs=1, flags=0):
+    """bfmht_plan_create with plan flags (PLAN_FULL_BLOCKS); returns the handle."""
+    st, keep = factors_struct(fs)
+    h = ctypes.c_void_p()
+    _check(lib.bfmht_plan_create_ex(ctypes.byref(st), int(precision), int(max_nrhs), int(flags), ctypes.byref(h)),
+           "bfmht_plan_create_ex")
+    del keep
+    return h.value
+
+
+def bfmht_plan_stored_entries(plan, transpose=False):
+    return lib.bfmht_plan_stored_entries(plan, 1 if transpose else 0)
+
+
 def bfmht_plan_device_bytes(plan):
     return lib.bfmht_plan_device_bytes(plan)
 
@@ -215,11 +237,13 @@ class Plan:
 
     apply(c)   -> f = Phi~ c      c: (m,) or (m, b) tensor on the plan's device
     apply_t(f) -> g = Phi~^T f    f: (n,) or (n, b)
+    full_blocks: store every ID block as the full P also for the forward apply
+    (by default blocks with the column-ID structure keep only T there).
     Element type: float64 for precision "f64", float32 otherwise.
     Calls run on the current torch stream of the plan's device.
     """
 
-    def __init__(self, fs, precision="f32", max_nrhs=64, device="cuda"):
+    def __init__(self, fs, precision="f32", max_nrhs=64, device="cuda", full_blocks=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bfmht.Plan needs a HIP device; there is no CPU path")
@@ -232,7 +256,9 @@ class Plan:
         self.precision = precision
         self.dtype = torch.float64 if self.prec == F64 else torch.float32
         self.n, self.m, self.L = int(fs["n"]), int(fs["m"]), int(fs["L"])
-        self.handle = bfmht_plan_create(fs, self.prec, max_nrhs)
+        self.handle = bfmht_plan_create_ex(fs, self.prec, max_nrhs, PLAN_FULL_BLOCKS if full_blocks else 0)
+        self.stored_fwd = bfmht_plan_stored_entries(self.handle, False)
+        self.stored_t = bfmht_plan_stored_entries(self.handle, True)
         nbytes = bfmht_plan_device_bytes(self.handle)
         self._dev = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._dev.data_ptr()

@@ -20,13 +20,24 @@
 namespace bfmht {
 
 // One forward GEMM job: dst rows = W (M x K, row stride ldw) * src rows.
+// A column interpolative decomposition P = [I T] Pi^T keeps, for every output
+// row i, one skeleton input row s_i whose column of P is the unit vector e_i.
+// The forward pool stores only T (the non-skeleton columns, in increasing
+// order) and the job adds the skeleton rows in its epilogue:
+//   y_i = x[s_i] + sum_t T[i, t] x[c_t]
+// The input rows of the reduction (c_t) and the skeleton rows (s_i) are listed
+// in the plan's row-index table at map_off: K entries c_t, then (when skel) M
+// entries s_i, all relative to in_row.  Blocks without that structure store P
+// itself with the identity list 0..K-1 and skel = 0.
 struct FwdJob {
-  int64_t w_off;   // element offset of W in the forward pool; -1 = identity (copy)
+  int64_t w_off;   // element offset of W (T or P) in the forward pool; -1 = identity (copy)
   int32_t M;       // output rows
-  int32_t K;       // input rows
+  int32_t K;       // rows of the reduction (columns of W)
   int32_t ldw;     // row stride of W in elements (K rounded up to 8)
-  int32_t in_row;  // first source row
+  int32_t in_row;  // first source row of the block's input
   int32_t out_row; // first destination row, or first row-map index when the stage has a row map
+  int32_t map_off; // first entry of the job's row indices in the index table (-1 for identity jobs)
+  int32_t skel;    // 1: add the M skeleton rows (compact ID block)
   int32_t pad;
 };
 
@@ -70,6 +81,7 @@ struct StageArgs {
   void *dst;
   int64_t ldd;
   const int32_t *rowmap;  // output row map of the forward leaf stage (perm_x), else nullptr
+  const int32_t *maps;    // forward stages: the plan's row-index table (see FwdJob)
   int32_t nrhs;
 };
 

@@ -126,13 +126,16 @@ struct Tiling {
 // (16-byte source rows and every column tile full, fixed per launch) the row
 // segment is one vector load.  No branches: the pipelined loop keeps exact
 // wait counts.
-template <typename T, int BN, bool FULL>
+// MAP: the reduction's rows come through the job's row-index list; `mrow` is
+// this thread's entry for the chunk (loaded one chunk ahead by the caller).
+template <typename T, int BN, bool FULL, bool MAP>
 __device__ __forceinline__ void load_x(T *xr, const StageArgs &a, int32_t base, int32_t nrows, int k0, int n0,
-                                       int tid) {
+                                       int tid, int mrow) {
   typedef Tiling<T, BN> Tl;
   const int k = tid % Tl::KC, c = (tid / Tl::KC) * Tl::XR;
   const int gk = k0 + k;
-  const T *row = static_cast<const T *>(a.src) + (int64_t)(base + min(gk, nrows - 1)) * a.lds;
+  const int64_t srow = (int64_t)base + (MAP ? mrow : min(gk, nrows - 1));
+  const T *row = static_cast<const T *>(a.src) + srow * a.lds;
   if constexpr (FULL) {
     copy_vec<T, Tl::XR>(xr, row + n0 + c);
   } else {
@@ -193,18 +196,23 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
 // off, factor rows are loaded for every block of the wave), so the compiler's
 // wait counts stay exact.  Ends with a barrier, so a following call may restage
 // the buffers.
-template <typename T, int BN, int FM, bool FULL>
+template <typename T, int BN, int FM, bool FULL, bool MAP>
 __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int nk,
-                                           const StageArgs &a, int32_t base, int n0, T *Xs, int tid, int lrow,
-                                           int lg, int nact) {
+                                           const StageArgs &a, int32_t base, const int32_t *rmap, int n0, T *Xs,
+                                           int tid, int lrow, int lg, int nact) {
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk <= 0) return;
   T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
-  // RHS first: the wait before staging it into LDS then leaves the factor loads
-  // in flight (loads complete in order).
+  const int kx = tid % Tl::KC;
+  int mrow = MAP ? rmap[min(kx, nk - 1)] : 0;
+  // RHS first, then the next chunk's row index, then the factor rows: loads
+  // complete in order, so the waits for the RHS (before staging it into LDS) and
+  // for the row index (before the next chunk's RHS loads) leave the factor loads
+  // in flight.
   auto load_chunk = [&](T (*w)[Tl::KL], int c) {
-    load_x<T, BN, FULL>(xB, a, base, nk, c * Tl::KC, n0, tid);
+    load_x<T, BN, FULL, MAP>(xB, a, base, nk, c * Tl::KC, n0, tid, mrow);
+    if (MAP) mrow = rmap[min((c + 1) * Tl::KC + kx, nk - 1)];
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
@@ -264,7 +272,9 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
-  gemm_block<T, BN, FM, FULL>(acc, wrow, J.K, a, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  const int32_t *rmap = a.maps + J.map_off;
+  gemm_block<T, BN, FM, FULL, true>(acc, wrow, J.K, a, J.in_row, rmap, n0, Xs, tid, lrow, lg, nact);
+  const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -274,7 +284,11 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
       for (int i = 0; i < 4; ++i) {
         const int gr = rbase + fm * 16 + acc_row(T(0), lane, i);
         const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.M && gc < a.nrhs) dst[out_row(a, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
+        if (gr < J.M && gc < a.nrhs) {
+          T v = acc[fm][fn][i];
+          if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + gr]) * a.lds + gc];  // skeleton row of output gr
+          dst[out_row(a, J.out_row, gr) * a.ldd + gc] = v;
+        }
       }
 }
 
@@ -305,7 +319,7 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
       wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
-    gemm_block<T, BN, FM, FULL>(acc, wrow, C.M, a, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block<T, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, nact);
   }
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
@@ -369,15 +383,16 @@ struct TilingB {
 // transposed.  Thread t takes rows 2 (t % 32) and 2 (t % 32) + 1 and the XP
 // columns of column group t / 32; the two rows' terms of one column are packed
 // into one 32-bit LDS word, so consecutive lanes write consecutive words.
-template <int NTERM, int BN, bool FULL>
+template <int NTERM, int BN, bool FULL, bool MAP>
 __device__ __forceinline__ void load_x_bf(float *xr, const StageArgs &a, int32_t base, int32_t nrows, int k0, int n0,
-                                          int tid) {
+                                          int tid, const int *mrow) {
   typedef TilingB<NTERM, BN> Tl;
   const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {  // clamped rows and columns, zeroed past the block / nrhs (no branches)
     const int gk = k0 + k + h;
-    const float *row = static_cast<const float *>(a.src) + (int64_t)(base + min(gk, nrows - 1)) * a.lds;
+    const int64_t srow = (int64_t)base + (MAP ? mrow[h] : min(gk, nrows - 1));
+    const float *row = static_cast<const float *>(a.src) + srow * a.lds;
     if constexpr (FULL) {
       copy_vec<float, Tl::XP>(xr + h * Tl::XP, row + n0 + c);
     } else {
@@ -464,17 +479,23 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
 // as gemm_block (no conditions in the loop body, tail peeled, final barrier).  Xs
 // holds 2 buffers per term: term t buffer j at Xs + (2 t + j) XBUF.  wrow[fm][t]:
 // term t of row fm.
-template <int NTERM, int BN, int FM, bool FULL>
+template <int NTERM, int BN, int FM, bool FULL, bool MAP>
 __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int nk,
-                                              const StageArgs &a, int32_t base, int n0, uint16_t *Xs, int tid,
-                                              int lrow, int lg, int nact) {
+                                              const StageArgs &a, int32_t base, const int32_t *rmap, int n0,
+                                              uint16_t *Xs, int tid, int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk <= 0) return;
   uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
-  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {  // RHS first, as in gemm_block
-    load_x_bf<NTERM, BN, FULL>(xB, a, base, nk, c * Tl::KC, n0, tid);
+  const int kx = 2 * (tid % 32);
+  int mrow[2] = {MAP ? rmap[min(kx, nk - 1)] : 0, MAP ? rmap[min(kx + 1, nk - 1)] : 0};
+  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {  // same order as in gemm_block
+    load_x_bf<NTERM, BN, FULL, MAP>(xB, a, base, nk, c * Tl::KC, n0, tid, mrow);
+    if (MAP) {
+      mrow[0] = rmap[min((c + 1) * Tl::KC + kx, nk - 1)];
+      mrow[1] = rmap[min((c + 1) * Tl::KC + kx + 1, nk - 1)];
+    }
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
@@ -540,7 +561,9 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  gemm_block_bf<NTERM, BN, FM, FULL>(acc, wrow, J.K, a, J.in_row, n0, Xs, tid, lrow, lg, nact);
+  const int32_t *rmap = a.maps + J.map_off;
+  gemm_block_bf<NTERM, BN, FM, FULL, true>(acc, wrow, J.K, a, J.in_row, rmap, n0, Xs, tid, lrow, lg, nact);
+  const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -550,7 +573,11 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
       for (int i = 0; i < 4; ++i) {
         const int gr = rbase + fm * 16 + acc_row(0.f, lane, i);
         const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.M && gc < a.nrhs) dst[out_row(a, J.out_row, gr) * a.ldd + gc] = acc[fm][fn][i];
+        if (gr < J.M && gc < a.nrhs) {
+          float v = acc[fm][fn][i];
+          if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + gr]) * a.lds + gc];  // skeleton row of output gr
+          dst[out_row(a, J.out_row, gr) * a.ldd + gc] = v;
+        }
       }
 }
 
@@ -583,7 +610,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
       wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
       wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    gemm_block_bf<NTERM, BN, FM, FULL>(acc, wrow, C.M, a, C.g_row, n0, Xs, tid, lrow, lg, nact);
+    gemm_block_bf<NTERM, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, nact);
   }
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);

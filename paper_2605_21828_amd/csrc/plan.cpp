@@ -68,7 +68,10 @@ struct bfmht_plan {
   std::vector<int64_t> level_rows;
   int64_t max_rows = 0;
   int64_t pool_elems = 0, tpool_elems = 0;
-  int64_t stored_entries = 0;  // factor entries that are read once per apply (no padding)
+  int64_t stored_entries = 0;      // factor entries of the transposed pool (read once per transposed apply)
+  int64_t stored_fwd = 0;          // factor entries of the forward pool (compact blocks store T only)
+  std::vector<int32_t> maps;       // forward jobs' row-index table
+  int64_t off_maps = 0;
   int64_t off_pool[3] = {0, 0, 0};   // forward pool, one region per term
   int64_t off_tpool[3] = {0, 0, 0};  // transposed pool
   int64_t off_fjobs = 0, off_bjobs = 0, off_tiles = 0, off_perm = 0, dev_bytes = 0;
@@ -134,6 +137,35 @@ bfmht_status validate(const bfmht_factors_host *f) {
   return BFMHT_OK;
 }
 
+// Column ID structure P = [I T] Pi^T (r x k, row-major): finds for every row i
+// a column holding exactly e_i (its skeleton column) and lists the other
+// columns in increasing order.  False when some row has none.
+bool split_id(const double *P, int64_t r, int64_t k, std::vector<int32_t> &jc, std::vector<int32_t> &jsk) {
+  if (!P || r <= 0 || r >= k) return false;
+  std::vector<int32_t> nz(k, 0), one_row(k, -1);
+  std::vector<char> bad(k, 0);
+  for (int64_t i = 0; i < r; ++i)
+    for (int64_t c = 0; c < k; ++c) {
+      const double v = P[i * k + c];
+      if (v == 0.0) continue;
+      ++nz[c];
+      if (v == 1.0) one_row[c] = (int32_t)i; else bad[c] = 1;
+    }
+  jsk.assign(r, -1);
+  std::vector<char> skel(k, 0);
+  for (int64_t c = 0; c < k; ++c)
+    if (nz[c] == 1 && !bad[c] && one_row[c] >= 0 && jsk[one_row[c]] < 0) {
+      jsk[one_row[c]] = (int32_t)c;
+      skel[c] = 1;
+    }
+  for (int64_t i = 0; i < r; ++i)
+    if (jsk[i] < 0) return false;
+  jc.clear();
+  for (int64_t c = 0; c < k; ++c)
+    if (!skel[c]) jc.push_back((int32_t)c);
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -143,7 +175,14 @@ const char *bfmht_version(void) { return "bfmht 0.1 gfx950"; }
 
 bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs,
                                bfmht_plan **out) {
+  return bfmht_plan_create_ex(f, prec, max_nrhs, 0, out);
+}
+
+bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs, int32_t flags,
+                                  bfmht_plan **out) {
   if (!out) return fail(BFMHT_EINVAL, "plan output pointer is NULL");
+  if (flags & ~BFMHT_PLAN_FULL_BLOCKS) return fail(BFMHT_EINVAL, "unknown plan flags");
+  const bool compact_ids = (flags & BFMHT_PLAN_FULL_BLOCKS) == 0;
   *out = nullptr;
   if (prec < BFMHT_F64 || prec > BFMHT_BF16X3) return fail(BFMHT_EINVAL, "unknown precision");
   if (max_nrhs < 1) return fail(BFMHT_EINVAL, "max_nrhs must be >= 1");
@@ -178,10 +217,16 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
   // order (n rows) and the scaled apply's scaled coefficients (m rows).
   p->max_rows = std::max<int64_t>(p->max_rows, std::max<int64_t>(f->n, f->m));
 
-  // Pool offsets of every stored block: W (rows x cols, stride ldw_of(cols)) in
-  // the forward pool and W^T (cols x rows, stride ldw_of(rows)) in the
-  // transposed pool, in the same block order.
-  struct Src { const double *ptr; int64_t rows, cols; };
+  // Pool offsets of every stored block: in the forward pool W (rows x cols,
+  // stride ldw_of(cols)), which for a compact ID block is T (its non-skeleton
+  // columns); in the transposed pool W^T = P^T (cols x rows, stride
+  // ldw_of(rows)); both in the same block order.
+  struct Src {
+    const double *ptr;
+    int64_t rows, cols;
+    bool compact;
+    std::vector<int32_t> jc, jsk;   // non-skeleton columns; skeleton column of every row
+  };
   std::vector<Src> blocks;
   std::vector<int64_t> woff_P((size_t)(L + 1) * nb, -1), woff_U(nb, -1);
   std::vector<int64_t> wtoff_P((size_t)(L + 1) * nb, -1), wtoff_U(nb, -1);
@@ -191,26 +236,58 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     const int64_t nf = 1ll << (L - lvl), i = q / nf, j = q % nf, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
     return (int64_t)f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1];
   };
+  std::vector<int64_t> bidx_P((size_t)(L + 1) * nb, -1);
   for (int lvl = 0; lvl <= L; ++lvl)
     for (int64_t q = 0; q < nb; ++q) {
       if (f->ident[lvl * nb + q]) continue;
       const int64_t r = f->rank[lvl * nb + q], k = rin_of(lvl, q);
+      Src b{r * k ? f->P + f->P_off[lvl * nb + q] : nullptr, r, k, false, {}, {}};
+      if (compact_ids) b.compact = split_id(b.ptr, r, k, b.jc, b.jsk);
+      const int64_t kf = b.compact ? (int64_t)b.jc.size() : k;
       woff_P[lvl * nb + q] = pool;
       wtoff_P[lvl * nb + q] = tpool;
-      blocks.push_back({r * k ? f->P + f->P_off[lvl * nb + q] : nullptr, r, k});
-      pool += r * ldw_of(k);
+      bidx_P[lvl * nb + q] = (int64_t)blocks.size();
+      pool += r * ldw_of(kf);
       tpool += k * ldw_of(r);
       p->stored_entries += r * k;
+      p->stored_fwd += r * kf;
+      blocks.push_back(std::move(b));
     }
   for (int64_t i = 0; i < nb; ++i) {
     const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
     woff_U[i] = pool;
     wtoff_U[i] = tpool;
-    blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r});
+    blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r, false, {}, {}});
     pool += rows * ldw_of(r);
     tpool += r * ldw_of(rows);
     p->stored_entries += rows * r;
+    p->stored_fwd += rows * r;
   }
+  // Row-index table entry of a forward job: the reduction's input rows, then
+  // (compact blocks) the skeleton rows; identity jobs have none.
+  auto add_map = [&](int64_t bi, int64_t k) -> int32_t {
+    const int32_t at = (int32_t)p->maps.size();
+    if (bi >= 0 && blocks[bi].compact) {
+      p->maps.insert(p->maps.end(), blocks[bi].jc.begin(), blocks[bi].jc.end());
+      p->maps.insert(p->maps.end(), blocks[bi].jsk.begin(), blocks[bi].jsk.end());
+    } else {
+      for (int64_t c = 0; c < k; ++c) p->maps.push_back((int32_t)c);
+    }
+    return at;
+  };
+  auto fjob = [&](int64_t w_off, int64_t bi, int64_t M, int64_t k, int64_t in_row, int64_t out_row) -> FwdJob {
+    FwdJob J{};
+    J.w_off = w_off;
+    J.M = (int32_t)M;
+    const bool cmp = bi >= 0 && blocks[bi].compact;
+    J.K = (int32_t)(cmp ? (int64_t)blocks[bi].jc.size() : k);
+    J.ldw = ldw_of(J.K);
+    J.in_row = (int32_t)in_row;
+    J.out_row = (int32_t)out_row;
+    J.map_off = w_off < 0 ? -1 : add_map(bi, k);
+    J.skel = cmp ? 1 : 0;
+    return J;
+  };
   p->pool_elems = pool;
   p->tpool_elems = tpool;
 
@@ -291,7 +368,7 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
       for (int64_t j = 0; j < nb; ++j) {
         const bool id = f->ident[j] != 0;
         const int64_t k = f->koff[j + 1] - f->koff[j];
-        fj.push_back({id ? -1 : woff_P[j], f->rank[j], (int32_t)k, ldw_of(k), (int32_t)f->koff[j], (int32_t)off[0][j], 0});
+        fj.push_back(fjob(id ? -1 : woff_P[j], bidx_P[j], f->rank[j], k, f->koff[j], off[0][j]));
         BwdJob b{};
         b.K = (int32_t)k;
         b.out_row = (int32_t)f->koff[j];
@@ -306,8 +383,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
           const int64_t q = i * nf + j, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
           const bool id = f->ident[lvl * nb + q] != 0;
           const int64_t k = rin_of(lvl, q);
-          fj.push_back({id ? -1 : woff_P[lvl * nb + q], f->rank[lvl * nb + q], (int32_t)k, ldw_of(k),
-                        (int32_t)off[lvl - 1][q1], (int32_t)off[lvl][q], 0});
+          fj.push_back(fjob(id ? -1 : woff_P[lvl * nb + q], bidx_P[lvl * nb + q], f->rank[lvl * nb + q], k,
+                            off[lvl - 1][q1], off[lvl][q]));
         }
       for (int64_t pp = 0; pp < (1ll << (lvl - 1)); ++pp)
         for (int64_t j = 0; j < nf; ++j) {
@@ -323,7 +400,7 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
     } else {
       for (int64_t i = 0; i < nb; ++i) {
         const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
-        fj.push_back({woff_U[i], (int32_t)rows, (int32_t)r, ldw_of(r), (int32_t)off[L][i], (int32_t)f->xoff[i], 0});
+        fj.push_back(fjob(woff_U[i], -1, rows, r, off[L][i], f->xoff[i]));
         BwdJob b{};
         b.K = (int32_t)r;
         b.out_row = (int32_t)off[L][i];
@@ -368,6 +445,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
   cur = align_up(cur + (int64_t)tiles.size() * (int64_t)sizeof(Tile), 256);
   p->off_perm = cur;
   cur = align_up(cur + f->n * 4, 256);
+  p->off_maps = cur;
+  cur = align_up(cur + (int64_t)p->maps.size() * 4, 256);
   p->dev_bytes = std::max<int64_t>(cur, 256);
 
   try {
@@ -394,16 +473,17 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
   };
   int64_t bo = 0, tbo = 0;
   for (const Src &b : blocks) {
-    const int64_t ld = ldw_of(b.cols), ldt = ldw_of(b.rows);
-    for (int64_t r = 0; r < b.rows; ++r)
-      for (int64_t c = 0; c < b.cols; ++c) {
-        const double x = b.ptr[r * b.cols + c];
-        put(p->off_pool, bo + r * ld + c, x);
-        put(p->off_tpool, tbo + c * ldt + r, x);
-      }
+    const int64_t kf = b.compact ? (int64_t)b.jc.size() : b.cols;
+    const int64_t ld = ldw_of(kf), ldt = ldw_of(b.rows);
+    for (int64_t r = 0; r < b.rows; ++r) {
+      for (int64_t c = 0; c < b.cols; ++c) put(p->off_tpool, tbo + c * ldt + r, b.ptr[r * b.cols + c]);
+      for (int64_t t = 0; t < kf; ++t) put(p->off_pool, bo + r * ld + t, b.ptr[r * b.cols + (b.compact ? b.jc[t] : t)]);
+    }
     bo += b.rows * ld;
     tbo += b.cols * ldt;
   }
+  if (!p->maps.empty()) std::memcpy(S + p->off_maps, p->maps.data(), p->maps.size() * 4);
+  std::vector<int32_t>().swap(p->maps);
   if (!fj.empty()) std::memcpy(S + p->off_fjobs, fj.data(), fj.size() * sizeof(FwdJob));
   if (!bj.empty()) std::memcpy(S + p->off_bjobs, bj.data(), bj.size() * sizeof(BwdJob));
   if (!tiles.empty()) std::memcpy(S + p->off_tiles, tiles.data(), tiles.size() * sizeof(Tile));
@@ -413,6 +493,11 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
 }
 
 int64_t bfmht_plan_device_bytes(const bfmht_plan *p) { return p ? p->dev_bytes : -1; }
+
+int64_t bfmht_plan_stored_entries(const bfmht_plan *p, int32_t transpose) {
+  if (!p) return -1;
+  return transpose ? p->stored_entries : p->stored_fwd;
+}
 
 int64_t bfmht_workspace_bytes(const bfmht_plan *p, int32_t nrhs) {
   if (!p || nrhs < 0) return -1;
@@ -477,6 +562,7 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h) {
   }
   // the forward leaf stage scatters its rows to the points' order
   a.rowmap = fwd && s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
+  a.maps = reinterpret_cast<const int32_t *>(p->dev + p->off_maps);
   return a;
 }
 

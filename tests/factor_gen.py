@@ -18,9 +18,12 @@ def _partition(rng, total, parts, allow_empty=True):
     return np.concatenate([[0], cuts, [total]]).astype(np.int64)
 
 
-def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=True, identity_values=False):
+def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=True, identity_values=False,
+                      p_id_form=0.0):
     """Random factor set.  identity_values=True makes every P the identity and
-    every U_i a 0/1 selection so that the apply is an exact permutation."""
+    every U_i a 0/1 selection so that the apply is an exact permutation.
+    p_id_form: probability that a non-identity block with 0 < rank < inputs has
+    the column-ID form P = [I T] Pi^T (r random columns hold e_1 .. e_r)."""
     rng = np.random.default_rng(seed)
     nb = 1 << L
     perm = rng.permutation(n).astype(np.int32)
@@ -48,6 +51,9 @@ def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=Tr
             rank[lvl, q] = r
             P_off[lvl, q] = off
             blk = rng.standard_normal((r, rin)) / np.sqrt(max(rin, 1))
+            if p_id_form > 0 and 0 < r < rin and rng.random() < p_id_form:
+                skel = rng.choice(rin, size=r, replace=False)
+                blk[:, skel] = np.eye(r)
             chunks.append(blk.ravel())
             off += blk.size
     U_off = np.zeros(nb, np.int64)

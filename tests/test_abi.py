@@ -115,3 +115,70 @@ def test_apply_before_upload_is_state_error(good):
 def test_destroy_null_is_noop():
     B.lib.bfmht_plan_destroy(None)
     assert B.lib.bfmht_version().startswith(b"bfmht")
+
+
+def _id_saving(fs):
+    """Entries the compact forward form drops: r^2 per ID-form block (the oracle's
+    view of the structure is not used; this reads the blocks directly)."""
+    L, nb = int(fs["L"]), 1 << int(fs["L"])
+    save = 0
+    for lvl in range(L + 1):
+        nf = 1 << (L - lvl)
+        for q in range(nb):
+            if fs["ident"][lvl, q] or fs["P_off"][lvl, q] < 0:
+                continue
+            r = int(fs["rank"][lvl, q])
+            if lvl == 0:
+                k = int(fs["koff"][q + 1] - fs["koff"][q])
+            else:
+                i, j = divmod(q, nf)
+                q1 = (i >> 1) * 2 * nf + 2 * j
+                k = int(fs["rank"][lvl - 1, q1] + fs["rank"][lvl - 1, q1 + 1])
+            if not 0 < r < k:
+                continue
+            P = fs["P"][fs["P_off"][lvl, q]:fs["P_off"][lvl, q] + r * k].reshape(r, k)
+            unit = [np.flatnonzero((P[:, j] == 1.0) & (np.count_nonzero(P[:, j]) == 1)) for j in range(k)]
+            rows = {int(u[0]) for u in unit if u.size}
+            if len(rows) == r:
+                save += r * r
+    return save
+
+
+@pytest.mark.parametrize("p_id_form", [0.0, 0.5, 1.0])
+def test_stored_entries_compact_and_full(p_id_form):
+    fs = random_factor_set(7, 400, 300, 4, max_rank=40, p_id_form=p_id_form)
+    full = int(fs["P"].size + fs["U"].size)
+    h = B.bfmht_plan_create_ex(fs, B.F32, 4, 0)
+    hf = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_FULL_BLOCKS)
+    try:
+        assert B.bfmht_plan_stored_entries(h, True) == full
+        assert B.bfmht_plan_stored_entries(hf, True) == full
+        assert B.bfmht_plan_stored_entries(hf, False) == full
+        save = _id_saving(fs)
+        assert (save > 0) == (p_id_form > 0)
+        assert B.bfmht_plan_stored_entries(h, False) == full - save
+    finally:
+        B.bfmht_plan_destroy(h)
+        B.bfmht_plan_destroy(hf)
+
+
+def test_id_block_with_a_perturbed_skeleton_stays_full():
+    fs = random_factor_set(8, 200, 150, 3, max_rank=30, p_id_form=1.0)
+    base = _id_saving(fs)
+    assert base > 0
+    P = fs["P"].copy()
+    P[np.flatnonzero(P == 1.0)[0]] = 1.0 + 2.0 ** -40   # one skeleton entry no longer exactly 1
+    bad = dict(fs, P=P)
+    h = B.bfmht_plan_create_ex(bad, B.F64, 1, 0)
+    try:
+        assert B.bfmht_plan_stored_entries(h, False) == int(P.size + fs["U"].size) - _id_saving(bad)
+        assert _id_saving(bad) < base
+    finally:
+        B.bfmht_plan_destroy(h)
+
+
+def test_plan_create_ex_rejects_unknown_flags(good):
+    with pytest.raises(B.BfmhtError) as e:
+        B.bfmht_plan_create_ex(good, B.F32, 1, 2)
+    assert e.value.status == B.EINVAL
+    assert B.bfmht_plan_stored_entries(None, 0) == -1
