@@ -41,22 +41,30 @@ struct FwdJob {
   int32_t pad;
 };
 
-// One consumer of a transposed job: the transposed copy of its forward block
-// (W^T, K x M) and where the incoming gradient rows live.
+// One consumer of a transposed job: rows [lo, hi) of the job's (logical) rows
+// reduce over M gradient rows with the stored W^T rows (one per logical row of
+// the range, row stride ldwt); the job's other rows take nothing from this
+// consumer's product.
 struct Cons {
-  int64_t wt_off;  // element offset of W^T in the transposed pool; -1 = identity consumer
-  int32_t M;       // columns of W^T = gradient rows read
+  int64_t wt_off;  // element offset of the range's first W^T row in the transposed pool; -1: no product
+                   // (an identity consumer: in a job without a row-index table it adds its g rows directly)
+  int32_t M;       // gradient rows read (rank of the consumer block)
   int32_t ldwt;    // row stride of W^T (M rounded up to 8)
-  int32_t g_row;   // first gradient row (or row-map index when the stage has a row map)
+  int32_t g_row;   // first gradient row
+  int32_t lo, hi;  // logical rows with a product
   int32_t pad;
 };
 
-// One transposed job: dst[out_row .. out_row+K) = sum_c W_c^T g_c.
+// One transposed job: dst[out_row .. out_row+K) = sum_c P_c^T g_c.  With a
+// row-index table (map_off >= 0) the K logical rows are a permutation of the
+// job's rows: entries map_off .. +K give each logical row's physical row, then
+// per consumer K entries give the g row that a skeleton row takes from that
+// consumer (-1: none).  The transposed pool at offset 0 holds a zero row.
 struct BwdJob {
   int32_t K;
   int32_t out_row;
   int32_t nc;      // number of consumers (1 or 2)
-  int32_t pad;
+  int32_t map_off; // -1: logical rows are physical rows, no skeleton rows
   Cons c[2];
 };
 

@@ -293,7 +293,10 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
 }
 
 // Transposed stage tile: dst[out_row .. out_row+K) = sum over consumers of
-// W_c^T g_c, identity consumers adding their gradient rows directly.
+// P_c^T g_c.  Each consumer reduces over the tile rows of its range [lo, hi)
+// (rows outside it read the pool's zero row, and a wave or tile that has none
+// of them skips the product); skeleton rows and identity consumers add their
+// gradient rows in the epilogue, and logical rows go to their physical rows.
 template <typename T, int BN, int FM, bool FULL>
 __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T *Xs) {
   typedef Tiling<T, BN> Tl;
@@ -314,15 +317,20 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
     if (ci >= J.nc) break;
     const Cons C = J.c[ci];
-    if (C.wt_off < 0) continue;
+    if (C.wt_off < 0 || C.hi <= tile.m0 || C.lo >= tile.m0 + 64 * FM) continue;   // no row of the tile reduces
+    const T *pool = static_cast<const T *>(a.pool);
     const T *wrow[FM];
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm)   // rows of W^T are columns of W
-      wrow[fm] = static_cast<const T *>(a.pool) + C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
-    gemm_block<T, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, nact);
+    for (int fm = 0; fm < FM; ++fm) {   // rows of W^T are columns of P
+      const int r = rbase + fm * 16 + lrow;
+      wrow[fm] = r >= C.lo && r < C.hi ? pool + C.wt_off + (int64_t)(r - C.lo) * C.ldwt : pool;
+    }
+    const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
+    gemm_block<T, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
+  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -333,13 +341,21 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
         const int gc = n0 + fn * 16 + lrow;
         if (gr < J.K && gc < a.nrhs) {
           T v = acc[fm][fn][i];
+          int pr = gr;
+          if (jm) {
+            pr = jm[gr];
 #pragma unroll
-          for (int ci = 0; ci < 2; ++ci)
-            if (ci < J.nc && J.c[ci].wt_off < 0) {
-              const int32_t b = J.c[ci].g_row;
-              v += src[(int64_t)(b + gr) * a.lds + gc];
-            }
-          dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+            for (int ci = 0; ci < 2; ++ci)
+              if (ci < J.nc) {
+                const int32_t g = jm[(ci + 1) * J.K + gr];   // skeleton row: this consumer's g row
+                if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + gc];
+              }
+          } else {
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci)
+              if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + gr) * a.lds + gc];
+          }
+          dst[(int64_t)(J.out_row + pr) * a.ldd + gc] = v;
         }
       }
 }
@@ -601,19 +617,22 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
     if (ci >= J.nc) break;
     const Cons C = J.c[ci];
-    if (C.wt_off < 0) continue;
+    if (C.wt_off < 0 || C.hi <= tile.m0 || C.lo >= tile.m0 + 64 * FM) continue;   // as in bwd_tile
     const uint16_t *wrow[FM][3];
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) {
-      const int64_t roff = C.wt_off + (int64_t)min(rbase + fm * 16 + lrow, J.K - 1) * C.ldwt;
+      const int r = rbase + fm * 16 + lrow;
+      const int64_t roff = r >= C.lo && r < C.hi ? C.wt_off + (int64_t)(r - C.lo) * C.ldwt : 0;
       wrow[fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
       wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
       wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    gemm_block_bf<NTERM, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, nact);
+    const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
+    gemm_block_bf<NTERM, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
   const float *src = static_cast<const float *>(a.src);
   float *dst = static_cast<float *>(a.dst);
+  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -624,13 +643,21 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
         const int gc = n0 + fn * 16 + lrow;
         if (gr < J.K && gc < a.nrhs) {
           float v = acc[fm][fn][i];
+          int pr = gr;
+          if (jm) {
+            pr = jm[gr];
 #pragma unroll
-          for (int ci = 0; ci < 2; ++ci)
-            if (ci < J.nc && J.c[ci].wt_off < 0) {
-              const int32_t b = J.c[ci].g_row;
-              v += src[(int64_t)(b + gr) * a.lds + gc];
-            }
-          dst[(int64_t)(J.out_row + gr) * a.ldd + gc] = v;
+            for (int ci = 0; ci < 2; ++ci)
+              if (ci < J.nc) {
+                const int32_t g = jm[(ci + 1) * J.K + gr];
+                if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + gc];
+              }
+          } else {
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci)
+              if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + gr) * a.lds + gc];
+          }
+          dst[(int64_t)(J.out_row + pr) * a.ldd + gc] = v;
         }
       }
 }

@@ -68,7 +68,7 @@ struct bfmht_plan {
   std::vector<int64_t> level_rows;
   int64_t max_rows = 0;
   int64_t pool_elems = 0, tpool_elems = 0;
-  int64_t stored_entries = 0;      // factor entries of the transposed pool (read once per transposed apply)
+  int64_t stored_t = 0;            // factor entries of the transposed pool (compact blocks: T^T only)
   int64_t stored_fwd = 0;          // factor entries of the forward pool (compact blocks store T only)
   std::vector<int32_t> maps;       // forward jobs' row-index table
   int64_t off_maps = 0;
@@ -217,10 +217,9 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   // order (n rows) and the scaled apply's scaled coefficients (m rows).
   p->max_rows = std::max<int64_t>(p->max_rows, std::max<int64_t>(f->n, f->m));
 
-  // Pool offsets of every stored block: in the forward pool W (rows x cols,
-  // stride ldw_of(cols)), which for a compact ID block is T (its non-skeleton
-  // columns); in the transposed pool W^T = P^T (cols x rows, stride
-  // ldw_of(rows)); both in the same block order.
+  // Forward pool offsets of every stored block: W (rows x cols, stride
+  // ldw_of(cols)), which for a compact ID block is T (its non-skeleton
+  // columns).  The transposed pool is laid out per transposed job below.
   struct Src {
     const double *ptr;
     int64_t rows, cols;
@@ -229,8 +228,7 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   };
   std::vector<Src> blocks;
   std::vector<int64_t> woff_P((size_t)(L + 1) * nb, -1), woff_U(nb, -1);
-  std::vector<int64_t> wtoff_P((size_t)(L + 1) * nb, -1), wtoff_U(nb, -1);
-  int64_t pool = 0, tpool = 0;
+  int64_t pool = 0;
   auto rin_of = [&](int lvl, int64_t q) -> int64_t {
     if (lvl == 0) return f->koff[q + 1] - f->koff[q];
     const int64_t nf = 1ll << (L - lvl), i = q / nf, j = q % nf, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
@@ -245,22 +243,18 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
       if (compact_ids) b.compact = split_id(b.ptr, r, k, b.jc, b.jsk);
       const int64_t kf = b.compact ? (int64_t)b.jc.size() : k;
       woff_P[lvl * nb + q] = pool;
-      wtoff_P[lvl * nb + q] = tpool;
       bidx_P[lvl * nb + q] = (int64_t)blocks.size();
       pool += r * ldw_of(kf);
-      tpool += k * ldw_of(r);
-      p->stored_entries += r * k;
       p->stored_fwd += r * kf;
       blocks.push_back(std::move(b));
     }
+  std::vector<int64_t> bidx_U(nb, -1);
   for (int64_t i = 0; i < nb; ++i) {
     const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
     woff_U[i] = pool;
-    wtoff_U[i] = tpool;
+    bidx_U[i] = (int64_t)blocks.size();
     blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r, false, {}, {}});
     pool += rows * ldw_of(r);
-    tpool += r * ldw_of(rows);
-    p->stored_entries += rows * r;
     p->stored_fwd += rows * r;
   }
   // Row-index table entry of a forward job: the reduction's input rows, then
@@ -289,7 +283,79 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
     return J;
   };
   p->pool_elems = pool;
-  p->tpool_elems = tpool;
+
+  // Transposed pool: a zero region first (the W^T row of any tile row that a
+  // consumer does not reduce over; as long as the longest row plus one
+  // reduction chunk), then each transposed job's consumers' W^T rows.
+  int64_t maxM = 0;
+  for (const Src &b : blocks) maxM = std::max<int64_t>(maxM, b.rows);
+  int64_t tpool = align_up(maxM + 64, 64);
+  struct TRow { int64_t off; int64_t blk; int32_t col; };   // W^T row = column col of block blk
+  std::vector<TRow> trows;
+  // A transposed job: dst rows [out_row, out_row + K) = sum over its consumers
+  // c of P_c^T g_c.  A consumer whose P_c has the column-ID form takes the
+  // skeleton rows straight from g_c and reduces over its other rows only.  The
+  // job's rows are then processed in a permuted (logical) order, sorted by
+  // (skeleton for consumer 0, skeleton for consumer 1) as SS, SN, NN, NS, so
+  // that each consumer's non-skeleton rows form one contiguous range; its W^T
+  // rows are stored for that range only, in logical order.
+  struct ConsIn { int64_t bi; bool ident; int32_t M; int32_t g_row; };
+  auto bjob = [&](int32_t K, int32_t out_row, int nc, const ConsIn *ci) -> BwdJob {
+    BwdJob J{};
+    J.K = K;
+    J.out_row = out_row;
+    J.nc = nc;
+    J.map_off = -1;
+    bool any = false;
+    for (int c = 0; c < nc; ++c) any = any || (!ci[c].ident && ci[c].bi >= 0 && blocks[ci[c].bi].compact);
+    std::vector<int32_t> omap(K), st[2];
+    for (int32_t k = 0; k < K; ++k) omap[k] = k;
+    int32_t lo[2] = {0, 0}, hi[2] = {K, K};
+    if (any) {
+      for (int c = 0; c < nc; ++c) {
+        st[c].assign(K, -1);   // g row of a skeleton row, -1 for a reduced row
+        if (ci[c].ident) {
+          for (int32_t k = 0; k < K; ++k) st[c][k] = k;
+        } else if (ci[c].bi >= 0 && blocks[ci[c].bi].compact) {
+          const Src &b = blocks[ci[c].bi];
+          for (int64_t i = 0; i < b.rows; ++i) st[c][b.jsk[i]] = (int32_t)i;
+        }
+      }
+      auto cls = [&](int32_t k) {
+        const bool s0 = st[0][k] >= 0, s1 = nc > 1 && st[1][k] >= 0;
+        return s0 ? (s1 ? 0 : 1) : (s1 ? 3 : 2);
+      };
+      std::stable_sort(omap.begin(), omap.end(), [&](int32_t x, int32_t y) { return cls(x) < cls(y); });
+      int32_t cnt[4] = {0, 0, 0, 0};
+      for (int32_t k = 0; k < K; ++k) ++cnt[cls(k)];
+      lo[0] = cnt[0] + cnt[1];
+      hi[0] = K;
+      lo[1] = cnt[0];
+      hi[1] = cnt[0] + cnt[1] + cnt[2];
+      J.map_off = (int32_t)p->maps.size();
+      p->maps.insert(p->maps.end(), omap.begin(), omap.end());
+      for (int c = 0; c < nc; ++c)
+        for (int32_t r = 0; r < K; ++r) p->maps.push_back(st[c][omap[r]]);
+    }
+    for (int c = 0; c < nc; ++c) {
+      Cons &C = J.c[c];
+      C.M = ci[c].M;
+      C.ldwt = ldw_of(C.M);
+      C.g_row = ci[c].g_row;
+      if (ci[c].ident) {   // identity consumer: no rows reduced (without maps the kernel adds g rows itself)
+        C.wt_off = -1;
+        C.lo = C.hi = 0;
+        continue;
+      }
+      C.lo = lo[c];
+      C.hi = C.M > 0 ? hi[c] : lo[c];
+      C.wt_off = tpool;
+      for (int32_t r = C.lo; r < C.hi; ++r) trows.push_back({tpool + (int64_t)(r - C.lo) * C.ldwt, ci[c].bi, omap[r]});
+      tpool += (int64_t)(C.hi - C.lo) * C.ldwt;
+      p->stored_t += (int64_t)(C.hi - C.lo) * C.M;
+    }
+    return J;
+  };
 
   // Stage tables.
   std::vector<FwdJob> fj;
@@ -339,8 +405,9 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   auto add_btiles = [&](StageDesc &s) {
     std::vector<std::pair<int64_t, int64_t>> jc;
     for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t) {
-      int64_t cost = 1;
-      for (int c = 0; c < bj[t].nc; ++c) cost += bj[t].c[c].M;
+      int64_t cost = 1;   // reduction length per tile row, averaged over the job's rows
+      for (int c = 0; c < bj[t].nc; ++c)
+        cost += (int64_t)bj[t].c[c].M * (bj[t].c[c].hi - bj[t].c[c].lo) / std::max<int32_t>(bj[t].K, 1);
       jc.push_back({cost, bj[t].K});
     }
     for (int h = 0; h < 2; ++h) {
@@ -348,15 +415,8 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
       s.nbtile[h] = order(jc, kTileRows << h);
     }
   };
-  auto cons_of = [&](int lvl, int64_t q) -> Cons {
-    Cons c;
-    const bool id = f->ident[lvl * nb + q] != 0;
-    c.wt_off = id ? -1 : wtoff_P[lvl * nb + q];
-    c.M = f->rank[lvl * nb + q];
-    c.ldwt = ldw_of(c.M);
-    c.g_row = (int32_t)off[lvl][q];
-    c.pad = 0;
-    return c;
+  auto cons_of = [&](int lvl, int64_t q) -> ConsIn {
+    return {bidx_P[lvl * nb + q], f->ident[lvl * nb + q] != 0, f->rank[lvl * nb + q], (int32_t)off[lvl][q]};
   };
   for (int lvl = 0; lvl <= L + 1; ++lvl) {
     StageDesc s{};
@@ -369,12 +429,8 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
         const bool id = f->ident[j] != 0;
         const int64_t k = f->koff[j + 1] - f->koff[j];
         fj.push_back(fjob(id ? -1 : woff_P[j], bidx_P[j], f->rank[j], k, f->koff[j], off[0][j]));
-        BwdJob b{};
-        b.K = (int32_t)k;
-        b.out_row = (int32_t)f->koff[j];
-        b.nc = 1;
-        b.c[0] = cons_of(0, j);
-        bj.push_back(b);
+        const ConsIn c0 = cons_of(0, j);
+        bj.push_back(bjob((int32_t)k, (int32_t)f->koff[j], 1, &c0));
       }
     } else if (lvl <= L) {
       const int64_t nf = 1ll << (L - lvl);
@@ -389,33 +445,23 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
       for (int64_t pp = 0; pp < (1ll << (lvl - 1)); ++pp)
         for (int64_t j = 0; j < nf; ++j) {
           const int64_t q1 = pp * 2 * nf + 2 * j;
-          BwdJob b{};
-          b.K = (int32_t)(f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1]);
-          b.out_row = (int32_t)off[lvl - 1][q1];
-          b.nc = 2;
-          b.c[0] = cons_of(lvl, (2 * pp) * nf + j);
-          b.c[1] = cons_of(lvl, (2 * pp + 1) * nf + j);
-          bj.push_back(b);
+          const ConsIn cs[2] = {cons_of(lvl, (2 * pp) * nf + j), cons_of(lvl, (2 * pp + 1) * nf + j)};
+          bj.push_back(bjob((int32_t)(f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1]),
+                            (int32_t)off[lvl - 1][q1], 2, cs));
         }
     } else {
       for (int64_t i = 0; i < nb; ++i) {
         const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
         fj.push_back(fjob(woff_U[i], -1, rows, r, off[L][i], f->xoff[i]));
-        BwdJob b{};
-        b.K = (int32_t)r;
-        b.out_row = (int32_t)off[L][i];
-        b.nc = 1;
-        b.c[0].wt_off = woff_U[i] >= 0 ? wtoff_U[i] : -1;
-        b.c[0].M = (int32_t)rows;
-        b.c[0].ldwt = ldw_of(rows);
-        b.c[0].g_row = (int32_t)f->xoff[i];
-        bj.push_back(b);
+        const ConsIn c0 = {bidx_U[i], false, (int32_t)rows, (int32_t)f->xoff[i]};
+        bj.push_back(bjob((int32_t)r, (int32_t)off[L][i], 1, &c0));
       }
     }
     s.nfjob = (int64_t)fj.size() - s.fjob0;
     s.nbjob = (int64_t)bj.size() - s.bjob0;
     p->stages.push_back(s);
   }
+  p->tpool_elems = tpool;
   for (auto &s : p->stages) {
     add_ftiles(s);
     add_btiles(s);
@@ -471,16 +517,17 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
       if (p->nterms == 3) reinterpret_cast<uint16_t *>(S + base[2])[e] = f32_to_bf16(r1 - bf16_to_f32(lo));
     }
   };
-  int64_t bo = 0, tbo = 0;
+  int64_t bo = 0;
   for (const Src &b : blocks) {
     const int64_t kf = b.compact ? (int64_t)b.jc.size() : b.cols;
-    const int64_t ld = ldw_of(kf), ldt = ldw_of(b.rows);
-    for (int64_t r = 0; r < b.rows; ++r) {
-      for (int64_t c = 0; c < b.cols; ++c) put(p->off_tpool, tbo + c * ldt + r, b.ptr[r * b.cols + c]);
+    const int64_t ld = ldw_of(kf);
+    for (int64_t r = 0; r < b.rows; ++r)
       for (int64_t t = 0; t < kf; ++t) put(p->off_pool, bo + r * ld + t, b.ptr[r * b.cols + (b.compact ? b.jc[t] : t)]);
-    }
     bo += b.rows * ld;
-    tbo += b.cols * ldt;
+  }
+  for (const TRow &t : trows) {
+    const Src &b = blocks[t.blk];
+    for (int64_t i = 0; i < b.rows; ++i) put(p->off_tpool, t.off + i, b.ptr[i * b.cols + t.col]);
   }
   if (!p->maps.empty()) std::memcpy(S + p->off_maps, p->maps.data(), p->maps.size() * 4);
   std::vector<int32_t>().swap(p->maps);
@@ -496,7 +543,7 @@ int64_t bfmht_plan_device_bytes(const bfmht_plan *p) { return p ? p->dev_bytes :
 
 int64_t bfmht_plan_stored_entries(const bfmht_plan *p, int32_t transpose) {
   if (!p) return -1;
-  return transpose ? p->stored_entries : p->stored_fwd;
+  return transpose ? p->stored_t : p->stored_fwd;
 }
 
 int64_t bfmht_workspace_bytes(const bfmht_plan *p, int32_t nrhs) {

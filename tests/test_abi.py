@@ -118,8 +118,8 @@ def test_destroy_null_is_noop():
 
 
 def _id_saving(fs):
-    """Entries the compact forward form drops: r^2 per ID-form block (the oracle's
-    view of the structure is not used; this reads the blocks directly)."""
+    """Entries the compact form drops: r^2 per ID-form block (read from the
+    blocks directly)."""
     L, nb = int(fs["L"]), 1 << int(fs["L"])
     save = 0
     for lvl in range(L + 1):
@@ -151,12 +151,13 @@ def test_stored_entries_compact_and_full(p_id_form):
     h = B.bfmht_plan_create_ex(fs, B.F32, 4, 0)
     hf = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_FULL_BLOCKS)
     try:
-        assert B.bfmht_plan_stored_entries(h, True) == full
         assert B.bfmht_plan_stored_entries(hf, True) == full
         assert B.bfmht_plan_stored_entries(hf, False) == full
         save = _id_saving(fs)
         assert (save > 0) == (p_id_form > 0)
+        # both directions drop the identity part of every ID-form block
         assert B.bfmht_plan_stored_entries(h, False) == full - save
+        assert B.bfmht_plan_stored_entries(h, True) == full - save
     finally:
         B.bfmht_plan_destroy(h)
         B.bfmht_plan_destroy(hf)
@@ -172,6 +173,7 @@ def test_id_block_with_a_perturbed_skeleton_stays_full():
     h = B.bfmht_plan_create_ex(bad, B.F64, 1, 0)
     try:
         assert B.bfmht_plan_stored_entries(h, False) == int(P.size + fs["U"].size) - _id_saving(bad)
+        assert B.bfmht_plan_stored_entries(h, True) == int(P.size + fs["U"].size) - _id_saving(bad)
         assert _id_saving(bad) < base
     finally:
         B.bfmht_plan_destroy(h)
