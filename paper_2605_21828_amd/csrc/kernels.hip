@@ -190,12 +190,15 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
 }
 
 // Reduction over one factor block: acc += W(rows of this wave) * src rows
-// base .. base+nk.  Chunks alternate between two register sets and two LDS
-// buffers; the loads of chunk c+1 are in flight while chunk c runs on the matrix
-// cores.  The loop body has no conditions (the last one or two chunks are peeled
-// off, factor rows are loaded for every block of the wave), so the compiler's
-// wait counts stay exact.  Ends with a barrier, so a following call may restage
-// the buffers.
+// base .. base+nk, chunk by chunk with the loads two chunks ahead: step c
+// issues chunk c+2's loads (register set (c+2) mod 3), runs chunk c on the
+// matrix cores from LDS buffer c mod 2, stages chunk c+1's RHS (loaded one step
+// earlier) into the other buffer and ends with the barrier that publishes it.
+// Load indices are clamped to the last chunk, so every step issues the same
+// loads and the loop body has no conditional memory operation (the compiler's
+// wait counts stay exact); the clamped repeats near the end are L2 hits and are
+// never multiplied.  Ends with a barrier, so a following call may restage the
+// buffers.
 template <typename T, int BN, int FM, bool FULL, bool MAP>
 __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int nk,
                                            const StageArgs &a, int32_t base, const int32_t *rmap, int n0, T *Xs,
@@ -203,48 +206,169 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk <= 0) return;
-  T wA[FM][Tl::KL], wB[FM][Tl::KL], xB[Tl::XR];
+  T w0[FM][Tl::KL], w1[FM][Tl::KL], w2[FM][Tl::KL], x0[Tl::XR], x1[Tl::XR], x2[Tl::XR];
   const int kx = tid % Tl::KC;
   int mrow = MAP ? rmap[min(kx, nk - 1)] : 0;
   // RHS first, then the next chunk's row index, then the factor rows: loads
   // complete in order, so the waits for the RHS (before staging it into LDS) and
   // for the row index (before the next chunk's RHS loads) leave the factor loads
   // in flight.
-  auto load_chunk = [&](T (*w)[Tl::KL], int c) {
-    load_x<T, BN, FULL, MAP>(xB, a, base, nk, c * Tl::KC, n0, tid, mrow);
+  auto load_chunk = [&](T (*w)[Tl::KL], T *x, int c) {
+    c = min(c, nchunk - 1);
+    load_x<T, BN, FULL, MAP>(x, a, base, nk, c * Tl::KC, n0, tid, mrow);
     if (MAP) mrow = rmap[min((c + 1) * Tl::KC + kx, nk - 1)];
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
-  T *X0 = Xs, *X1 = Xs + Tl::XBUF;
-  load_chunk(wA, 0);
-  store_x<T, BN>(X0, xB, tid);
+  auto step = [&](T (*wc)[Tl::KL], const T *xn, T (*wl)[Tl::KL], T *xl, int c) {
+    load_chunk(wl, xl, c + 2);
+    mma_chunk<T, BN, FM>(acc, wc, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
+    store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xn, tid);
+    __syncthreads();
+  };
+  load_chunk(w0, x0, 0);
+  load_chunk(w1, x1, 1);
+  store_x<T, BN>(Xs, x0, tid);
   __syncthreads();
-  int c = 0;
-  for (; c + 2 < nchunk; c += 2) {
-    load_chunk(wB, c + 1);
-    mma_chunk<T, BN, FM>(acc, wA, X0, lrow, lg, nact);
-    store_x<T, BN>(X1, xB, tid);
-    __syncthreads();
-    load_chunk(wA, c + 2);
-    mma_chunk<T, BN, FM>(acc, wB, X1, lrow, lg, nact);
-    store_x<T, BN>(X0, xB, tid);
-    __syncthreads();
+  for (int c = 0;; c += 3) {
+    step(w0, x1, w2, x2, c);
+    if (c + 1 >= nchunk) break;
+    step(w1, x2, w0, x0, c + 1);
+    if (c + 2 >= nchunk) break;
+    step(w2, x0, w1, x1, c + 2);
+    if (c + 3 >= nchunk) break;
   }
-  // one or two chunks left; the last one always runs from wA (one code path)
-  const bool two = c + 1 < nchunk;
-  if (two) {
-    load_chunk(wB, c + 1);
-    mma_chunk<T, BN, FM>(acc, wA, X0, lrow, lg, nact);
-    store_x<T, BN>(X1, xB, tid);
-    __syncthreads();
+}
+
+// Tile epilogues.  Every index a lane needs (output rows, skeleton rows) is
+// loaded first and every added value next, with clamped addresses and no
+// per-element branch, so the loads go out together and the lane waits once;
+// only the stores are predicated.  Accumulator element (fm, fn, i) holds job
+// row rbase + 16 fm + acc_row(i) and column n0 + 16 fn + lane % 16.
+
+// Forward: dst[out row] = acc (+ the skeleton row of a compact block).
+template <typename T, int BN, int FM, typename Acc>
+__device__ __forceinline__ void fwd_epilogue(const StageArgs &a, const FwdJob &J, const int32_t *rmap,
+                                             Acc (*acc)[BN / 16], int rbase, int n0, int lane) {
+  constexpr int FN = BN / 16;
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  const int lrow = lane & 15;
+  int gr[FM][4], orow[FM][4];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gr[fm][i] = min(rbase + fm * 16 + acc_row(T(0), lane, i), J.M - 1);
+  if (a.rowmap) {
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-      for (int i = 0; i < Tl::KL; ++i) wA[fm][i] = wB[fm][i];
+      for (int i = 0; i < 4; ++i) orow[fm][i] = a.rowmap[J.out_row + gr[fm][i]];
+  } else {
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) orow[fm][i] = J.out_row + gr[fm][i];
   }
-  mma_chunk<T, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, nact);
-  __syncthreads();
+  if (J.skel) {   // skeleton rows: index, then values, all loads in flight together
+    int srow[FM][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) srow[fm][i] = J.in_row + rmap[J.K + gr[fm][i]];
+    T x[FM][FN][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          x[fm][fn][i] = src[(int64_t)srow[fm][i] * a.lds + min(n0 + fn * 16 + lrow, a.nrhs - 1)];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[fm][fn][i] += x[fm][fn][i];
+  }
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gc = n0 + fn * 16 + lrow;
+        if (rbase + fm * 16 + acc_row(T(0), lane, i) < J.M && gc < a.nrhs)
+          dst[(int64_t)orow[fm][i] * a.ldd + gc] = acc[fm][fn][i];
+      }
+}
+
+// Transposed: dst[out_row + physical row] = acc + the gradient rows that
+// skeleton rows (or identity consumers) take.  Rows that take nothing from a
+// consumer read its first gradient row (a cached line) and add zero.
+template <typename T, int BN, int FM, typename Acc>
+__device__ __forceinline__ void bwd_epilogue(const StageArgs &a, const BwdJob &J, Acc (*acc)[BN / 16], int rbase,
+                                             int n0, int lane) {
+  constexpr int FN = BN / 16;
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  const int lrow = lane & 15;
+  const bool two = J.nc > 1;
+  int gr[FM][4], prow[FM][4], g[2][FM][4];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gr[fm][i] = min(rbase + fm * 16 + acc_row(T(0), lane, i), J.K - 1);
+  bool add[2];
+  if (J.map_off >= 0) {
+    const int32_t *jm = a.maps + J.map_off;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        prow[fm][i] = jm[gr[fm][i]];
+        g[0][fm][i] = jm[J.K + gr[fm][i]];
+        g[1][fm][i] = jm[(two ? 2 : 1) * J.K + gr[fm][i]];   // a one-consumer job repeats consumer 0 (unused)
+      }
+    add[0] = true;
+    add[1] = two;
+  } else {
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) prow[fm][i] = g[0][fm][i] = g[1][fm][i] = gr[fm][i];
+    add[0] = J.c[0].wt_off < 0;
+    add[1] = two && J.c[1].wt_off < 0;
+  }
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {
+    if (!add[ci]) continue;
+    const int64_t base = J.c[ci].g_row;
+    T x[FM][FN][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          x[fm][fn][i] = src[(base + max(g[ci][fm][i], 0)) * a.lds + min(n0 + fn * 16 + lrow, a.nrhs - 1)];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[fm][fn][i] += g[ci][fm][i] >= 0 ? x[fm][fn][i] : T(0);
+  }
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gc = n0 + fn * 16 + lrow;
+        if (rbase + fm * 16 + acc_row(T(0), lane, i) < J.K && gc < a.nrhs)
+          dst[(int64_t)(J.out_row + prow[fm][i]) * a.ldd + gc] = acc[fm][fn][i];
+      }
 }
 
 // Forward stage tile: dst[out rows] = W (M x K) * src[in_row .. in_row+K).
@@ -274,22 +398,7 @@ __device__ __forceinline__ void fwd_tile(const StageArgs &a, int tix, int ny, T 
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
   const int32_t *rmap = a.maps + J.map_off;
   gemm_block<T, BN, FM, FULL, true>(acc, wrow, J.K, a, J.in_row, rmap, n0, Xs, tid, lrow, lg, nact);
-  const T *src = static_cast<const T *>(a.src);
-  T *dst = static_cast<T *>(a.dst);
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < Tl::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = rbase + fm * 16 + acc_row(T(0), lane, i);
-        const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.M && gc < a.nrhs) {
-          T v = acc[fm][fn][i];
-          if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + gr]) * a.lds + gc];  // skeleton row of output gr
-          dst[out_row(a, J.out_row, gr) * a.ldd + gc] = v;
-        }
-      }
+  fwd_epilogue<T, BN, FM>(a, J, rmap, acc, rbase, n0, lane);
 }
 
 // Transposed stage tile: dst[out_row .. out_row+K) = sum over consumers of
@@ -328,36 +437,7 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
     const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
     gemm_block<T, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
-  const T *src = static_cast<const T *>(a.src);
-  T *dst = static_cast<T *>(a.dst);
-  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < Tl::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = rbase + fm * 16 + acc_row(T(0), lane, i);
-        const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.K && gc < a.nrhs) {
-          T v = acc[fm][fn][i];
-          int pr = gr;
-          if (jm) {
-            pr = jm[gr];
-#pragma unroll
-            for (int ci = 0; ci < 2; ++ci)
-              if (ci < J.nc) {
-                const int32_t g = jm[(ci + 1) * J.K + gr];   // skeleton row: this consumer's g row
-                if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + gc];
-              }
-          } else {
-#pragma unroll
-            for (int ci = 0; ci < 2; ++ci)
-              if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + gr) * a.lds + gc];
-          }
-          dst[(int64_t)(J.out_row + pr) * a.ldd + gc] = v;
-        }
-      }
+  bwd_epilogue<T, BN, FM>(a, J, acc, rbase, n0, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,12 +451,16 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
 // -> k assignment, so any internal ordering of k is summed the same way.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);  // finite inputs: round to nearest, ties to even
-  return (uint16_t)(u >> 16);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two values rounded to bf16 (round to nearest even) in one instruction
+// (v_cvt_pk_bf16_f32): a in the low half, b in the high half.
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bf16_lo_f32(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi_f32(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 __device__ __forceinline__ v4f mfma_bf16(const uint4 &a, const uint4 &b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
@@ -431,16 +515,16 @@ __device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int ti
   const int k = 2 * (tid % 32), c = (tid / 32) * Tl::XP;
 #pragma unroll
   for (int i = 0; i < Tl::XP; ++i) {
-    uint32_t w[3] = {0, 0, 0};
+    // rows k (low half) and k + 1 (high half) of one column, split term by term
+    uint32_t w[3];
+    float r0 = xr[i], r1 = xr[Tl::XP + i];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const float x = xr[h * Tl::XP + i];
-      const uint16_t t0 = f32_to_bf16_rne(x);
-      const float r = x - bf16_to_f32(t0);
-      const uint16_t t1 = f32_to_bf16_rne(r);
-      w[0] |= (uint32_t)t0 << (16 * h);
-      w[1] |= (uint32_t)t1 << (16 * h);
-      if constexpr (NTERM == 3) w[2] |= (uint32_t)f32_to_bf16_rne(r - bf16_to_f32(t1)) << (16 * h);
+    for (int t = 0; t < NTERM; ++t) {
+      w[t] = cvt_pk_bf16(r0, r1);
+      if (t + 1 < NTERM) {
+        r0 -= bf16_lo_f32(w[t]);
+        r1 -= bf16_hi_f32(w[t]);
+      }
     }
 #pragma unroll
     for (int t = 0; t < NTERM; ++t)
@@ -579,22 +663,7 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
   const int32_t *rmap = a.maps + J.map_off;
   gemm_block_bf<NTERM, BN, FM, FULL, true>(acc, wrow, J.K, a, J.in_row, rmap, n0, Xs, tid, lrow, lg, nact);
-  const float *src = static_cast<const float *>(a.src);
-  float *dst = static_cast<float *>(a.dst);
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < Tl::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = rbase + fm * 16 + acc_row(0.f, lane, i);
-        const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.M && gc < a.nrhs) {
-          float v = acc[fm][fn][i];
-          if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + gr]) * a.lds + gc];  // skeleton row of output gr
-          dst[out_row(a, J.out_row, gr) * a.ldd + gc] = v;
-        }
-      }
+  fwd_epilogue<float, BN, FM>(a, J, rmap, acc, rbase, n0, lane);
 }
 
 template <int NTERM, int BN, int FM, bool FULL>
@@ -630,36 +699,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
     const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
     gemm_block_bf<NTERM, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
-  const float *src = static_cast<const float *>(a.src);
-  float *dst = static_cast<float *>(a.dst);
-  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
-#pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-    for (int fn = 0; fn < Tl::FN; ++fn)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = rbase + fm * 16 + acc_row(0.f, lane, i);
-        const int gc = n0 + fn * 16 + lrow;
-        if (gr < J.K && gc < a.nrhs) {
-          float v = acc[fm][fn][i];
-          int pr = gr;
-          if (jm) {
-            pr = jm[gr];
-#pragma unroll
-            for (int ci = 0; ci < 2; ++ci)
-              if (ci < J.nc) {
-                const int32_t g = jm[(ci + 1) * J.K + gr];
-                if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + gc];
-              }
-          } else {
-#pragma unroll
-            for (int ci = 0; ci < 2; ++ci)
-              if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + gr) * a.lds + gc];
-          }
-          dst[(int64_t)(J.out_row + pr) * a.ldd + gc] = v;
-        }
-      }
+  bwd_epilogue<float, BN, FM>(a, J, acc, rbase, n0, lane);
 }
 
 // ---------------------------------------------------------------------------
