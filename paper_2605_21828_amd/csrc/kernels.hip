@@ -206,7 +206,7 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
   typedef Tiling<T, BN> Tl;
   const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
   if (nchunk <= 0) return;
-  T w0[FM][Tl::KL], w1[FM][Tl::KL], w2[FM][Tl::KL], x0[Tl::XR], x1[Tl::XR], x2[Tl::XR];
+  T w0[FM][Tl::KL], w1[FM][Tl::KL], w2[FM][Tl::KL], x0[Tl::XR], x1[Tl::XR];
   const int kx = tid % Tl::KC;
   int mrow = MAP ? rmap[min(kx, nk - 1)] : 0;
   // RHS first, then the next chunk's row index, then the factor rows: loads
@@ -220,6 +220,7 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
   };
+  // factor chunk c lives in register set c mod 3, RHS chunk c in set c mod 2
   auto step = [&](T (*wc)[Tl::KL], const T *xn, T (*wl)[Tl::KL], T *xl, int c) {
     load_chunk(wl, xl, c + 2);
     mma_chunk<T, BN, FM>(acc, wc, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
@@ -230,13 +231,19 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
   load_chunk(w1, x1, 1);
   store_x<T, BN>(Xs, x0, tid);
   __syncthreads();
-  for (int c = 0;; c += 3) {
-    step(w0, x1, w2, x2, c);
+  for (int c = 0;; c += 6) {
+    step(w0, x1, w2, x0, c);
     if (c + 1 >= nchunk) break;
-    step(w1, x2, w0, x0, c + 1);
+    step(w1, x0, w0, x1, c + 1);
     if (c + 2 >= nchunk) break;
-    step(w2, x0, w1, x1, c + 2);
+    step(w2, x1, w1, x0, c + 2);
     if (c + 3 >= nchunk) break;
+    step(w0, x0, w2, x1, c + 3);
+    if (c + 4 >= nchunk) break;
+    step(w1, x1, w0, x0, c + 4);
+    if (c + 5 >= nchunk) break;
+    step(w2, x0, w1, x1, c + 5);
+    if (c + 6 >= nchunk) break;
   }
 }
 
