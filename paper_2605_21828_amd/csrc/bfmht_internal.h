@@ -154,6 +154,7 @@ struct SegPack {
 static_assert(sizeof(SegPack) <= 4096, "launch arguments are limited to 4 KB");
 
 // One launch over `items` work items of the pack's segments (item0 relative to the pack).
-int launch_batched_stage(int prec, const SegPack &pack, int64_t items, void *stream);
+// One batched launch of segments that share the direction and the tile shape (bn x 64 fm).
+int launch_batched_stage(int prec, bool fwd, int bn, int fm, const SegPack &pack, int64_t items, void *stream);
 
 }  // namespace bfmht

@@ -848,37 +848,17 @@ int launch_scale_rows(int esz, const void *s, const void *src, int64_t lds, int6
 
 // ---------------------------------------------------------------------------
 // Many instances of uneven size per launch.  A batched apply runs one launch
-// per stage position (and per group of kSegsPerLaunch instances): launch k
-// holds the k-th stage of its instances, each workgroup decoding (segment,
-// tile, column tile) from its block index through the segments' first-item
-// offsets.  Stages of one instance are ordered by the launch boundaries, so no
-// workgroup ever waits on another.  The segments are launch arguments.
+// per stage position, tile shape (and group of kSegsPerLaunch instances):
+// launch k holds the k-th stage of its instances that use this tile shape,
+// each workgroup decoding (segment, tile, column tile) from its block index
+// through the segments' first-item offsets.  Stages of one instance are
+// ordered by the launch boundaries, so no workgroup ever waits on another.
+// The segments are launch arguments.  One kernel per tile shape keeps its
+// register count (and so its occupancy) that of the single-instance kernels.
 
-template <int P, bool FWD, bool FULL>
-__device__ __forceinline__ void run_segment_w(const Segment &S, int tix, int ny, void *lds) {
-  const bool tall = S.fm == 2;
-  switch (S.bn) {
-    case 16:
-      if (tall) run_tile<P, FWD, 16, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 16, 1, FULL>(S.a, tix, ny, lds);
-      break;
-    case 32:
-      if (tall) run_tile<P, FWD, 32, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 32, 1, FULL>(S.a, tix, ny, lds);
-      break;
-    default:
-      if (tall) run_tile<P, FWD, 64, 2, FULL>(S.a, tix, ny, lds); else run_tile<P, FWD, 64, 1, FULL>(S.a, tix, ny, lds);
-      break;
-  }
-}
-
-template <int P, bool FWD>
-__device__ __forceinline__ void run_segment(const Segment &S, int tix, int ny, void *lds) {
-  if (S.a.vec && S.a.nrhs % S.bn == 0) run_segment_w<P, FWD, true>(S, tix, ny, lds);
-  else run_segment_w<P, FWD, false>(S, tix, ny, lds);
-}
-
-template <int P>
+template <int P, bool FWD, int BN, int FM>
 __global__ __launch_bounds__(kNT) void batched_stage_kernel(SegPack pack) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, 64>::bytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, BN>::bytes];
   const int64_t g = blockIdx.x;
   int32_t lo = 0, hi = pack.nseg - 1;  // last segment whose first item is <= g
   while (lo < hi) {
@@ -888,26 +868,39 @@ __global__ __launch_bounds__(kNT) void batched_stage_kernel(SegPack pack) {
   const Segment S = pack.s[lo];  // by value: the selected segment only
   const int64_t t = g - S.item0;
   const int tix = (int)(t % S.a.ntiles), ny = (int)(t / S.a.ntiles);
-  if (S.fwd) run_segment<P, true>(S, tix, ny, lds);
-  else run_segment<P, false>(S, tix, ny, lds);
+  if (S.a.vec && S.a.nrhs % BN == 0) run_tile<P, FWD, BN, FM, true>(S.a, tix, ny, lds);
+  else run_tile<P, FWD, BN, FM, false>(S.a, tix, ny, lds);
 }
 
-int launch_batched_stage(int prec, const SegPack &pack, int64_t items, void *stream) {
+namespace {
+template <int P, bool FWD, int BN>
+void launch_batched_bn(int fm, const SegPack &pack, dim3 grid, hipStream_t s) {
+  if (fm == 2) hipLaunchKernelGGL((batched_stage_kernel<P, FWD, BN, 2>), grid, dim3(kNT), 0, s, pack);
+  else hipLaunchKernelGGL((batched_stage_kernel<P, FWD, BN, 1>), grid, dim3(kNT), 0, s, pack);
+}
+template <int P, bool FWD>
+void launch_batched_dir(int bn, int fm, const SegPack &pack, dim3 grid, hipStream_t s) {
+  if (bn == 16) launch_batched_bn<P, FWD, 16>(fm, pack, grid, s);
+  else if (bn == 32) launch_batched_bn<P, FWD, 32>(fm, pack, grid, s);
+  else launch_batched_bn<P, FWD, 64>(fm, pack, grid, s);
+}
+template <int P>
+void launch_batched_p(bool fwd, int bn, int fm, const SegPack &pack, dim3 grid, hipStream_t s) {
+  if (fwd) launch_batched_dir<P, true>(bn, fm, pack, grid, s);
+  else launch_batched_dir<P, false>(bn, fm, pack, grid, s);
+}
+}  // namespace
+
+int launch_batched_stage(int prec, bool fwd, int bn, int fm, const SegPack &pack, int64_t items, void *stream) {
   if (items == 0) return 0;
+  if ((bn != 16 && bn != 32 && bn != 64) || (fm != 1 && fm != 2)) return (int)hipErrorInvalidValue;
   const dim3 grid((unsigned)items);
+  hipStream_t s = (hipStream_t)stream;
   switch (prec) {
-    case P_F64:
-      hipLaunchKernelGGL((batched_stage_kernel<P_F64>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
-      break;
-    case P_F32:
-      hipLaunchKernelGGL((batched_stage_kernel<P_F32>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
-      break;
-    case P_BF16X2:
-      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X2>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
-      break;
-    case P_BF16X3:
-      hipLaunchKernelGGL((batched_stage_kernel<P_BF16X3>), grid, dim3(kNT), 0, (hipStream_t)stream, pack);
-      break;
+    case P_F64: launch_batched_p<P_F64>(fwd, bn, fm, pack, grid, s); break;
+    case P_F32: launch_batched_p<P_F32>(fwd, bn, fm, pack, grid, s); break;
+    case P_BF16X2: launch_batched_p<P_BF16X2>(fwd, bn, fm, pack, grid, s); break;
+    case P_BF16X3: launch_batched_p<P_BF16X3>(fwd, bn, fm, pack, grid, s); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

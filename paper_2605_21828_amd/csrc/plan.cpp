@@ -881,34 +881,40 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
     }
     maxS = std::max(maxS, per[i].size());
   }
-  // Launch k runs the k-th stage of every instance (in groups of at most
-  // kSegsPerLaunch, passed as launch arguments); segments without items are
-  // left out.
+  // Launch k runs the k-th stage of every instance, one launch per tile shape
+  // (in groups of at most kSegsPerLaunch segments, passed as launch
+  // arguments); segments without items are left out.
   for (size_t k = 0; k < maxS; ++k) {
-    SegPack pack{};
-    int64_t item = 0;
-    auto flush = [&]() -> bfmht_status {
-      if (pack.nseg == 0) return BFMHT_OK;
-      if (item >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
-      const int rc = launch_batched_stage(plans[0]->prec, pack, item, stream);
+    SegPack pack[3][2];
+    int64_t item[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int b = 0; b < 3; ++b)
+      for (int h = 0; h < 2; ++h) pack[b][h].nseg = 0;
+    auto flush = [&](int b, int h) -> bfmht_status {
+      if (pack[b][h].nseg == 0) return BFMHT_OK;
+      if (item[b][h] >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
+      const int rc = launch_batched_stage(plans[0]->prec, fwd, 16 << b, h + 1, pack[b][h], item[b][h], stream);
       if (rc) return fail(BFMHT_EHIP, std::string("batched launch: ") + hipGetErrorString((hipError_t)rc));
-      pack.nseg = 0;
-      item = 0;
+      pack[b][h].nseg = 0;
+      item[b][h] = 0;
       return BFMHT_OK;
     };
     for (int32_t i = 0; i < count; ++i) {
       if (k >= per[i].size() || per[i][k].nitems == 0) continue;
       Segment sg = per[i][k];
-      sg.item0 = item;
-      item += sg.nitems;
-      pack.s[pack.nseg++] = sg;
-      if (pack.nseg == kSegsPerLaunch) {
-        st = flush();
+      const int b = sg.bn == 16 ? 0 : (sg.bn == 32 ? 1 : 2), h = sg.fm == 2 ? 1 : 0;
+      sg.item0 = item[b][h];
+      item[b][h] += sg.nitems;
+      pack[b][h].s[pack[b][h].nseg++] = sg;
+      if (pack[b][h].nseg == kSegsPerLaunch) {
+        st = flush(b, h);
         if (st != BFMHT_OK) return st;
       }
     }
-    st = flush();
-    if (st != BFMHT_OK) return st;
+    for (int b = 0; b < 3; ++b)
+      for (int h = 0; h < 2; ++h) {
+        st = flush(b, h);
+        if (st != BFMHT_OK) return st;
+      }
   }
   return BFMHT_OK;
 }
