@@ -83,6 +83,12 @@ def roofline_for(prec, F, n, m, b, apply_ms, launches):
     return r
 
 
+def level_bytes(fs, b, s_x):
+    """Implementation bytes of one apply: every level vector (sum of the ranks of
+    a level, b columns) written once and read once."""
+    return 2.0 * float(np.asarray(fs["rank"], dtype=np.int64).sum()) * b * s_x
+
+
 def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -697,6 +703,9 @@ def main():
                      "frac": achieved / peak, "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per launch",
                      "alg_bytes_per_launch": alg_bytes32 / launches,
+                     # level vectors written by one stage and read by the next: not
+                     # algorithmic (intermediate), reported beside it
+                     "impl_bytes_per_launch": level_bytes(fs, b, 4) / launches,
                      "kernel": "stage_kernel<P_F32, forward> (all stage launches of one FP32 apply)",
                      "per_launch_alg_flops": flops / launches,
                      "avg_launch_ms": ms_fwd / launches},
