@@ -48,15 +48,25 @@ __global__ __launch_bounds__(kLsqrThreads) void sub_partial_kernel(const T *y, i
 }
 
 // norm[j] = sqrt(sum over blocks of partial[blk][j]); inv[j] = 1 / norm[j] (0 for a zero column).
+// One workgroup per column: thread t sums blocks t, t + 256, ... in order, then a
+// fixed halving tree in LDS, so the result does not depend on timing.
 template <typename T>
-__global__ void finish_norm_kernel(const T *partial, int nblk, int b, T *norm, T *inv) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= b) return;
+__global__ __launch_bounds__(kLsqrThreads) void finish_norm_kernel(const T *partial, int nblk, int b, T *norm, T *inv) {
+  __shared__ T red[kLsqrThreads];
+  const int j = blockIdx.x;
   T s = 0;
-  for (int k = 0; k < nblk; ++k) s += partial[(int64_t)k * b + j];
-  const T nv = sqrt(s);
-  norm[j] = nv;
-  inv[j] = nv > T(0) ? T(1) / nv : T(0);
+  for (int k = threadIdx.x; k < nblk; k += kLsqrThreads) s += partial[(int64_t)k * b + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kLsqrThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const T nv = sqrt(red[0]);
+    norm[j] = nv;
+    inv[j] = nv > T(0) ? T(1) / nv : T(0);
+  }
 }
 
 // u[r][j] *= inv[j]
@@ -133,7 +143,7 @@ static int normalize_t(const void *y, int64_t ldy, int64_t rows, int b, const vo
   hipLaunchKernelGGL((sub_partial_kernel<T>), dim3(nblk, (b + kCols - 1) / kCols), dim3(kLsqrThreads), 0, s,
                      static_cast<const T *>(y), ldy, rows, b, static_cast<const T *>(coef), static_cast<T *>(u),
                      static_cast<T *>(partial));
-  hipLaunchKernelGGL((finish_norm_kernel<T>), dim3((b + 63) / 64), dim3(64), 0, s, static_cast<const T *>(partial),
+  hipLaunchKernelGGL((finish_norm_kernel<T>), dim3(b), dim3(kLsqrThreads), 0, s, static_cast<const T *>(partial),
                      nblk, b, static_cast<T *>(norm), static_cast<T *>(inv));
   hipLaunchKernelGGL((scale_cols_kernel<T>), dim3(grid_for(rows * b)), dim3(kLsqrThreads), 0, s, static_cast<T *>(u),
                      rows, b, static_cast<const T *>(inv));

@@ -132,6 +132,34 @@ def test_tall_tiles_match_oracle(gpu, instances, prec):
         assert od.rel_err_cols(_np(p.apply_t(_t(f, _dt(prec)))), ob.apply_transpose(fs, f))[0] <= tol, case
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16x2", 1e-4)])
+def test_batched_compact_mixed_shapes_match_oracle(gpu, prec, tol):
+    """ID-form blocks (compact applies) in every instance, and a different tile
+    shape per instance, so one stage position runs several per-shape launches."""
+    from paper_2605_21828_amd import bfmht as B
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    sets = [random_factor_set(s + 100, n, m, L, max_rank=r, p_id_form=0.8) for s, n, m, L, r, _ in CASES]
+    shapes = [(64, 16), (128, 32), (64, 64), (128, 16), (64, 32), (128, 64), (64, 16)]
+    plans = []
+    for fs, c, sh in zip(sets, CASES, shapes):
+        p = Plan(fs, prec, max_nrhs=max(1, c[5]))
+        for k in range(B.bfmht_plan_num_stages(p.handle)):
+            B.bfmht_plan_set_tile(p.handle, 0, k, *sh)
+            B.bfmht_plan_set_tile(p.handle, 1, k, *sh)
+        plans.append(p)
+    rng = np.random.default_rng(8)
+    cs = [rng.standard_normal((int(fs["m"]), c[5])) for fs, c in zip(sets, CASES)]
+    fv = [rng.standard_normal((int(fs["n"]), c[5])) for fs, c in zip(sets, CASES)]
+    batch = Batch(plans)
+    ys = batch.run([_t(c, _dt(prec)) for c in cs])
+    gs = batch.run([_t(f, _dt(prec)) for f in fv], transpose=True)
+    for fs, c, f, y, g, case in zip(sets, cs, fv, ys, gs, CASES):
+        if case[5] == 0:
+            continue
+        assert od.rel_err_cols(_np(y), ob.apply(fs, c))[0] <= tol, case
+        assert od.rel_err_cols(_np(g), ob.apply_transpose(fs, f))[0] <= tol, case
+
+
 @pytest.mark.skip(reason="single persistent launch with inter-workgroup waits is switched off: two runs "
                          "stalled past the silence limit inside the stream sync (no fault) and the cause "
                          "was not shown on the CPU; batched applies use one launch per stage position")
