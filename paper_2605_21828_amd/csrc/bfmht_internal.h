@@ -106,6 +106,10 @@ constexpr int kTileRows = 64;
 // (16, 32 or 64) RHS columns; a.tiles must be the list built for that height.
 // Returns 0 or a hipError_t value.
 int launch_fwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
+// Few right-hand sides: the vector-FMA stage kernel over the 64-row tile list
+// (FP32/FP64, 1 <= nrhs <= kGemvMaxRhs).
+constexpr int kGemvMaxRhs = 4;
+int launch_gemv_stage(int prec, bool fwd, const StageArgs &a, void *stream);
 int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
 
 // dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).
@@ -136,9 +140,9 @@ int lsqr_init(int esz, void *x, int64_t ldx, void *w, const void *v, int64_t row
 struct Segment {
   StageArgs a;
   int32_t fwd;     // 1: forward stage, 0: transposed stage
-  int32_t bn;      // RHS columns per tile (16, 32, 64)
+  int32_t bn;      // RHS columns per tile (16, 32, 64); with fm = 0 the vector-FMA column count (1, 2, 4)
   int32_t ny;      // column tiles
-  int32_t fm;      // 16-row blocks per wave (tile height 64 fm)
+  int32_t fm;      // 16-row blocks per wave (tile height 64 fm); 0: vector-FMA kernel, 64-row tiles
   int64_t item0;   // first work item (block index) of this segment in its launch
   int64_t nitems;  // a.ntiles * ny
 };
@@ -156,5 +160,7 @@ static_assert(sizeof(SegPack) <= 4096, "launch arguments are limited to 4 KB");
 // One launch over `items` work items of the pack's segments (item0 relative to the pack).
 // One batched launch of segments that share the direction and the tile shape (bn x 64 fm).
 int launch_batched_stage(int prec, bool fwd, int bn, int fm, const SegPack &pack, int64_t items, void *stream);
+// One batched launch of few-RHS segments (each nrhs <= b, b in {1, 2, 4}) on the vector-FMA kernel.
+int launch_batched_gemv(int prec, bool fwd, int b, const SegPack &pack, int64_t items, void *stream);
 
 }  // namespace bfmht

@@ -789,6 +789,260 @@ int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *str
 }
 
 // ---------------------------------------------------------------------------
+// Few right-hand sides (nrhs <= kGemvMaxRhs, FP32/FP64): the apply is a chain
+// of matrix-vector products, bound by streaming the factors, and an MFMA tile
+// would leave most of its columns idle.  This kernel keeps the stage's jobs,
+// 64-row tiles and row-index tables, and computes with vector FMAs instead:
+// 16 lanes share one factor row (16-byte loads, 256 contiguous bytes per row
+// per instruction for FP32), a wave streams 4 rows at a time, and the
+// reduction's RHS rows (B columns each, gathered through the row-index list in
+// the forward direction) are staged into LDS kGemvKX rows per pass.
+
+constexpr int kGemvKX = 512;   // reduction rows staged per pass
+
+// Stage reduction rows [k0, k0 + kGemvKX) of one block (nk rows from source
+// row base, through rmap when MAP) as Xs[k][B]; zero past nk and past nrhs.
+template <typename T, int B, bool MAP>
+__device__ __forceinline__ void gemv_stage_x(T *Xs, const StageArgs &a, int32_t base, const int32_t *rmap, int nk,
+                                             int k0) {
+  const T *src = static_cast<const T *>(a.src);
+  for (int k = threadIdx.x; k < kGemvKX; k += kNT) {
+    const int gk = min(k0 + k, nk - 1);
+    const int64_t row = (int64_t)base + (MAP ? rmap[gk] : gk);
+    const bool ok = k0 + k < nk;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const T v = src[row * a.lds + min(j, a.nrhs - 1)];
+      Xs[k * B + j] = ok && j < a.nrhs ? v : T(0);
+    }
+  }
+}
+
+// acc[it][j] += sum over this lane's k of W[row it][k] X[k][j] for the staged
+// pass (k0 .. k0 + kGemvKX).  wrow[it]: this lane group's factor row it; kmax[it]:
+// the last 16-byte piece inside that row's storage (reads past the block read a
+// valid piece and meet zero RHS rows).
+template <typename T, int B>
+__device__ __forceinline__ void gemv_pass(T (*acc)[B], const T *const *wrow, const int *kmax, const T *Xs, int nk,
+                                          int k0, int kl) {
+  constexpr int VW = 16 / (int)sizeof(T), KS = 16 * VW;
+  const int kend = min(nk - k0, kGemvKX);
+#pragma unroll 2
+  for (int s = 0; s * KS < kend; ++s) {
+    const int kk = s * KS + kl * VW;
+    T x[VW][B];
+#pragma unroll
+    for (int v = 0; v < VW; ++v)
+#pragma unroll
+      for (int j = 0; j < B; ++j) x[v][j] = Xs[(kk + v) * B + j];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      T w[VW];
+      copy_vec<T, VW>(w, wrow[it] + min(k0 + kk, kmax[it]));
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[it][j] += w[v] * x[v][j];
+    }
+  }
+}
+
+// Sum acc over the 16 lanes of a row group; afterwards every lane holds the sums.
+template <typename T, int B>
+__device__ __forceinline__ void gemv_reduce(T (*acc)[B]) {
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+#pragma unroll
+      for (int m = 8; m >= 1; m >>= 1) acc[it][j] += __shfl_xor(acc[it][j], m, 16);
+}
+
+// v[j] for a lane-varying j < B, by bit masks (a select chain would be turned
+// into an indexed private-memory load).
+template <typename T, int B>
+__device__ __forceinline__ T pick_col(const T (&v)[B], int j) {
+  typedef typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type U;
+  U r = 0;
+#pragma unroll
+  for (int q = 0; q < B; ++q) r |= __builtin_bit_cast(U, v[q]) & (U)(-(int64_t)(j == q));
+  return __builtin_bit_cast(T, r);
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void gemv_fwd_tile(const StageArgs &a, int tix, T *Xs) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  const Tile tile = a.tiles[tix];
+  if (tile.job < 0) return;
+  const FwdJob J = static_cast<const FwdJob *>(a.jobs)[tile.job];
+  if (J.w_off < 0) {
+    copy_tile<T, 16>(a, J, tile.m0, kTileRows, 0);
+    return;
+  }
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, rg = lane >> 4, kl = lane & 15;
+  const int32_t *rmap = a.maps + J.map_off;
+  const T *wrow[4];
+  int kmax[4], gr[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    gr[it] = tile.m0 + 16 * wave + 4 * it + rg;
+    wrow[it] = static_cast<const T *>(a.pool) + J.w_off + (int64_t)min(gr[it], J.M - 1) * J.ldw;
+    kmax[it] = J.ldw - VW;
+  }
+  T acc[4][B];
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[it][j] = T(0);
+  for (int k0 = 0; k0 < J.K; k0 += kGemvKX) {
+    __syncthreads();
+    gemv_stage_x<T, B, true>(Xs, a, J.in_row, rmap, J.K, k0);
+    __syncthreads();
+    gemv_pass<T, B>(acc, wrow, kmax, Xs, J.K, k0, kl);
+  }
+  gemv_reduce<T, B>(acc);
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  const int j = min(kl, a.nrhs - 1);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int r = min(gr[it], J.M - 1);
+    T v = pick_col<T, B>(acc[it], kl);
+    if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + r]) * a.lds + j];
+    if (gr[it] < J.M && kl < a.nrhs) dst[out_row(a, J.out_row, r) * a.ldd + kl] = v;
+  }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void gemv_bwd_tile(const StageArgs &a, int tix, T *Xs) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  const Tile tile = a.tiles[tix];
+  if (tile.job < 0) return;
+  const BwdJob J = static_cast<const BwdJob *>(a.jobs)[tile.job];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, rg = lane >> 4, kl = lane & 15;
+  int gr[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) gr[it] = tile.m0 + 16 * wave + 4 * it + rg;
+  T acc[4][B];
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[it][j] = T(0);
+  const T *pool = static_cast<const T *>(a.pool);
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {
+    if (ci >= J.nc) break;
+    const Cons C = J.c[ci];
+    if (C.wt_off < 0 || C.hi <= tile.m0 || C.lo >= tile.m0 + kTileRows) continue;   // no row of the tile reduces
+    const T *wrow[4];
+    int kmax[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {   // rows outside [lo, hi) read the pool's zero row (long enough for any M)
+      const bool in = gr[it] >= C.lo && gr[it] < C.hi;
+      wrow[it] = in ? pool + C.wt_off + (int64_t)(gr[it] - C.lo) * C.ldwt : pool;
+      kmax[it] = in ? C.ldwt - VW : 1 << 30;
+    }
+    for (int k0 = 0; k0 < C.M; k0 += kGemvKX) {
+      __syncthreads();
+      gemv_stage_x<T, B, false>(Xs, a, C.g_row, nullptr, C.M, k0);
+      __syncthreads();
+      gemv_pass<T, B>(acc, wrow, kmax, Xs, C.M, k0, kl);
+    }
+  }
+  gemv_reduce<T, B>(acc);
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  const int j = min(kl, a.nrhs - 1);
+  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int r = min(gr[it], J.K - 1);
+    T v = pick_col<T, B>(acc[it], kl);
+    int pr = r;
+    if (jm) {
+      pr = jm[r];
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci)
+        if (ci < J.nc) {
+          const int32_t g = jm[(ci + 1) * J.K + r];
+          if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + j];
+        }
+    } else {
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci)
+        if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + r) * a.lds + j];
+    }
+    if (gr[it] < J.K && kl < a.nrhs) dst[(int64_t)(J.out_row + pr) * a.ldd + kl] = v;
+  }
+}
+
+template <typename T, bool FWD, int B>
+__global__ __launch_bounds__(kNT) void gemv_stage_kernel(StageArgs a) {
+  __shared__ __attribute__((aligned(16))) T Xs[kGemvKX * B];
+  if constexpr (FWD) gemv_fwd_tile<T, B>(a, blockIdx.x, Xs);
+  else gemv_bwd_tile<T, B>(a, blockIdx.x, Xs);
+}
+
+namespace {
+template <typename T, bool FWD>
+int launch_gemv_t(const StageArgs &a, void *stream) {
+  const dim3 grid((unsigned)a.ntiles);
+  hipStream_t s = (hipStream_t)stream;
+  if (a.nrhs == 1) hipLaunchKernelGGL((gemv_stage_kernel<T, FWD, 1>), grid, dim3(kNT), 0, s, a);
+  else if (a.nrhs == 2) hipLaunchKernelGGL((gemv_stage_kernel<T, FWD, 2>), grid, dim3(kNT), 0, s, a);
+  else hipLaunchKernelGGL((gemv_stage_kernel<T, FWD, 4>), grid, dim3(kNT), 0, s, a);
+  return (int)hipGetLastError();
+}
+}  // namespace
+
+// Batched form: segments (stage k of several instances, each with nrhs <= B)
+// decoded from the block index as in batched_stage_kernel.
+template <typename T, bool FWD, int B>
+__global__ __launch_bounds__(kNT) void batched_gemv_kernel(SegPack pack) {
+  __shared__ __attribute__((aligned(16))) T Xs[kGemvKX * B];
+  const int64_t g = blockIdx.x;
+  int32_t lo = 0, hi = pack.nseg - 1;  // last segment whose first item is <= g
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (pack.s[mid].item0 <= g) lo = mid; else hi = mid - 1;
+  }
+  const Segment S = pack.s[lo];
+  const int tix = (int)(g - S.item0);
+  if constexpr (FWD) gemv_fwd_tile<T, B>(S.a, tix, Xs);
+  else gemv_bwd_tile<T, B>(S.a, tix, Xs);
+}
+
+namespace {
+template <typename T, bool FWD>
+int launch_batched_gemv_t(int b, const SegPack &pack, dim3 grid, hipStream_t s) {
+  if (b == 1) hipLaunchKernelGGL((batched_gemv_kernel<T, FWD, 1>), grid, dim3(kNT), 0, s, pack);
+  else if (b == 2) hipLaunchKernelGGL((batched_gemv_kernel<T, FWD, 2>), grid, dim3(kNT), 0, s, pack);
+  else hipLaunchKernelGGL((batched_gemv_kernel<T, FWD, 4>), grid, dim3(kNT), 0, s, pack);
+  return (int)hipGetLastError();
+}
+}  // namespace
+
+int launch_batched_gemv(int prec, bool fwd, int b, const SegPack &pack, int64_t items, void *stream) {
+  if (items == 0) return 0;
+  if (b != 1 && b != 2 && b != 4) return (int)hipErrorInvalidValue;
+  const dim3 grid((unsigned)items);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == P_F64) return fwd ? launch_batched_gemv_t<double, true>(b, pack, grid, s)
+                                : launch_batched_gemv_t<double, false>(b, pack, grid, s);
+  if (prec == P_F32) return fwd ? launch_batched_gemv_t<float, true>(b, pack, grid, s)
+                                : launch_batched_gemv_t<float, false>(b, pack, grid, s);
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_gemv_stage(int prec, bool fwd, const StageArgs &a, void *stream) {
+  if (a.ntiles == 0) return 0;
+  if (a.nrhs < 1 || a.nrhs > kGemvMaxRhs) return (int)hipErrorInvalidValue;
+  if (prec == P_F64) return fwd ? launch_gemv_t<double, true>(a, stream) : launch_gemv_t<double, false>(a, stream);
+  if (prec == P_F32) return fwd ? launch_gemv_t<float, true>(a, stream) : launch_gemv_t<float, false>(a, stream);
+  return (int)hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
 // Row gather into tree order: dst[t] = src[perm[t]] (rows of nrhs elements).
 // The transposed apply reads its input through this copy, so every stage
 // kernel reads contiguous rows.

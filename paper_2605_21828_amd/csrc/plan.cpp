@@ -661,10 +661,17 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
     if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
   }
   const int S = (int)p->stages.size();
+  const bool gemv = nrhs <= kGemvMaxRhs && (p->prec == BFMHT_F32 || p->prec == BFMHT_F64);
   for (int k = 0; k < S; ++k) {
     const int si = fwd ? k : S - 1 - k;
     const StageDesc &s = p->stages[si];
     const int d = fwd ? 0 : 1;
+    if (gemv) {   // few right-hand sides: vector FMAs over the 64-row tiles
+      StageArgs a = stage_io(p, s, fwd, kTileRows, in, ldin, out, ldout, nrhs, buf);
+      const int e = launch_gemv_stage(p->prec, fwd, a, stream);
+      if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
+      continue;
+    }
     const int rows = p->rows[d][si], cols = pick_cols(p->cols[d][si], nrhs);
     StageArgs a = stage_io(p, s, fwd, rows, in, ldin, out, ldout, nrhs, buf);
     const int e = fwd ? launch_fwd_stage(p->prec, a, rows, cols, stream) : launch_bwd_stage(p->prec, a, rows, cols, stream);
@@ -866,55 +873,68 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
       if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
     }
     const int S = (int)p->stages.size();
+    const bool gemv = nrhs[i] <= kGemvMaxRhs && (p->prec == BFMHT_F32 || p->prec == BFMHT_F64);
     for (int k = 0; k < S; ++k) {
       const int si = fwd ? k : S - 1 - k;
       Segment sg{};
       const int d = fwd ? 0 : 1;
-      const int rows = p->rows[d][si];
+      const int rows = gemv ? kTileRows : p->rows[d][si];
       sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);
       sg.fwd = fwd ? 1 : 0;
-      sg.fm = rows / kTileRows;
-      sg.bn = pick_cols(p->cols[d][si], nrhs[i]);
-      sg.ny = (nrhs[i] + sg.bn - 1) / sg.bn;
+      if (gemv) {   // few right-hand sides: the vector-FMA kernel, as for a single apply
+        sg.fm = 0;
+        sg.bn = nrhs[i] <= 2 ? nrhs[i] : 4;
+        sg.ny = 1;
+      } else {
+        sg.fm = rows / kTileRows;
+        sg.bn = pick_cols(p->cols[d][si], nrhs[i]);
+        sg.ny = (nrhs[i] + sg.bn - 1) / sg.bn;
+      }
       sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
       per[i].push_back(sg);
     }
     maxS = std::max(maxS, per[i].size());
   }
-  // Launch k runs the k-th stage of every instance, one launch per tile shape
-  // (in groups of at most kSegsPerLaunch segments, passed as launch
-  // arguments); segments without items are left out.
+  // Launch k runs the k-th stage of every instance, one launch per kernel kind
+  // (MFMA tile shape bn x 64 fm, or the vector-FMA kernel for b columns), in
+  // groups of at most kSegsPerLaunch segments passed as launch arguments;
+  // segments without items are left out.  Buckets 0..5: MFMA (bn 16/32/64 x
+  // fm 1/2); 6..8: vector FMA (b 1/2/4).
   for (size_t k = 0; k < maxS; ++k) {
-    SegPack pack[3][2];
-    int64_t item[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int b = 0; b < 3; ++b)
-      for (int h = 0; h < 2; ++h) pack[b][h].nseg = 0;
-    auto flush = [&](int b, int h) -> bfmht_status {
-      if (pack[b][h].nseg == 0) return BFMHT_OK;
-      if (item[b][h] >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
-      const int rc = launch_batched_stage(plans[0]->prec, fwd, 16 << b, h + 1, pack[b][h], item[b][h], stream);
+    constexpr int NB = 9;
+    SegPack pack[NB];
+    int64_t item[NB];
+    for (int q = 0; q < NB; ++q) {
+      pack[q].nseg = 0;
+      item[q] = 0;
+    }
+    auto flush = [&](int q) -> bfmht_status {
+      if (pack[q].nseg == 0) return BFMHT_OK;
+      if (item[q] >= (1ll << 31)) return fail(BFMHT_EINVAL, "a batched launch has more than 2^31 work items");
+      const int rc = q < 6 ? launch_batched_stage(plans[0]->prec, fwd, 16 << (q >> 1), (q & 1) + 1, pack[q], item[q], stream)
+                           : launch_batched_gemv(plans[0]->prec, fwd, 1 << (q - 6), pack[q], item[q], stream);
       if (rc) return fail(BFMHT_EHIP, std::string("batched launch: ") + hipGetErrorString((hipError_t)rc));
-      pack[b][h].nseg = 0;
-      item[b][h] = 0;
+      pack[q].nseg = 0;
+      item[q] = 0;
       return BFMHT_OK;
     };
     for (int32_t i = 0; i < count; ++i) {
       if (k >= per[i].size() || per[i][k].nitems == 0) continue;
       Segment sg = per[i][k];
-      const int b = sg.bn == 16 ? 0 : (sg.bn == 32 ? 1 : 2), h = sg.fm == 2 ? 1 : 0;
-      sg.item0 = item[b][h];
-      item[b][h] += sg.nitems;
-      pack[b][h].s[pack[b][h].nseg++] = sg;
-      if (pack[b][h].nseg == kSegsPerLaunch) {
-        st = flush(b, h);
+      const int q = sg.fm == 0 ? 6 + (sg.bn == 1 ? 0 : (sg.bn == 2 ? 1 : 2))
+                               : 2 * (sg.bn == 16 ? 0 : (sg.bn == 32 ? 1 : 2)) + (sg.fm == 2 ? 1 : 0);
+      sg.item0 = item[q];
+      item[q] += sg.nitems;
+      pack[q].s[pack[q].nseg++] = sg;
+      if (pack[q].nseg == kSegsPerLaunch) {
+        st = flush(q);
         if (st != BFMHT_OK) return st;
       }
     }
-    for (int b = 0; b < 3; ++b)
-      for (int h = 0; h < 2; ++h) {
-        st = flush(b, h);
-        if (st != BFMHT_OK) return st;
-      }
+    for (int q = 0; q < NB; ++q) {
+      st = flush(q);
+      if (st != BFMHT_OK) return st;
+    }
   }
   return BFMHT_OK;
 }

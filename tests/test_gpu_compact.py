@@ -42,7 +42,7 @@ def _np(x):
 
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x2"])
-@pytest.mark.parametrize("nrhs", [1, 37, 64])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5, 37, 64])
 def test_compact_forward_vs_oracle(gpu, case, prec, nrhs):
     import torch
     from paper_2605_21828_amd.bfmht import Plan
