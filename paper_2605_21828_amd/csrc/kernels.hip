@@ -805,45 +805,70 @@ constexpr int kGemvKX = 512;   // reduction rows staged per pass
 template <typename T, int B, bool MAP>
 __device__ __forceinline__ void gemv_stage_x(T *Xs, const StageArgs &a, int32_t base, const int32_t *rmap, int nk,
                                              int k0) {
+  static_assert(kGemvKX % kNT == 0, "whole rows per thread");
+  constexpr int U = kGemvKX / kNT;
   const T *src = static_cast<const T *>(a.src);
-  for (int k = threadIdx.x; k < kGemvKX; k += kNT) {
-    const int gk = min(k0 + k, nk - 1);
-    const int64_t row = (int64_t)base + (MAP ? rmap[gk] : gk);
+  // row indices first, then every value, then the (zero-masked) LDS stores
+  int64_t row[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int gk = min(k0 + (int)threadIdx.x + u * kNT, nk - 1);
+    row[u] = ((int64_t)base + (MAP ? rmap[gk] : gk)) * a.lds;
+  }
+  T v[U][B];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[u][j] = src[row[u] + min(j, a.nrhs - 1)];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = (int)threadIdx.x + u * kNT;
     const bool ok = k0 + k < nk;
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const T v = src[row * a.lds + min(j, a.nrhs - 1)];
-      Xs[k * B + j] = ok && j < a.nrhs ? v : T(0);
-    }
+    for (int j = 0; j < B; ++j) Xs[k * B + j] = ok && j < a.nrhs ? v[u][j] : T(0);
   }
 }
 
 // acc[it][j] += sum over this lane's k of W[row it][k] X[k][j] for the staged
 // pass (k0 .. k0 + kGemvKX).  wrow[it]: this lane group's factor row it; kmax[it]:
 // the last 16-byte piece inside that row's storage (reads past the block read a
-// valid piece and meet zero RHS rows).
+// valid piece and meet zero RHS rows).  w0 holds the pass's first step, loaded
+// by the caller before the RHS staging so that the factor stream starts at once.
 template <typename T, int B>
-__device__ __forceinline__ void gemv_pass(T (*acc)[B], const T *const *wrow, const int *kmax, const T *Xs, int nk,
-                                          int k0, int kl) {
-  constexpr int VW = 16 / (int)sizeof(T), KS = 16 * VW;
-  const int kend = min(nk - k0, kGemvKX);
-#pragma unroll 2
-  for (int s = 0; s * KS < kend; ++s) {
-    const int kk = s * KS + kl * VW;
-    T x[VW][B];
+__device__ __forceinline__ void gemv_load(T (*w)[16 / sizeof(T)], const T *const *wrow, const int *kmax, int k) {
+  constexpr int VW = 16 / (int)sizeof(T);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) copy_vec<T, VW>(w[it], wrow[it] + min(k, kmax[it]));
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void gemv_fma(T (*acc)[B], const T (*w)[16 / sizeof(T)], const T *Xs, int kk) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  T x[VW][B];
+#pragma unroll
+  for (int v = 0; v < VW; ++v)
+#pragma unroll
+    for (int j = 0; j < B; ++j) x[v][j] = Xs[(kk + v) * B + j];
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
 #pragma unroll
     for (int v = 0; v < VW; ++v)
 #pragma unroll
-      for (int j = 0; j < B; ++j) x[v][j] = Xs[(kk + v) * B + j];
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      T w[VW];
-      copy_vec<T, VW>(w, wrow[it] + min(k0 + kk, kmax[it]));
-#pragma unroll
-      for (int v = 0; v < VW; ++v)
-#pragma unroll
-        for (int j = 0; j < B; ++j) acc[it][j] += w[v] * x[v][j];
-    }
+      for (int j = 0; j < B; ++j) acc[it][j] += w[it][v] * x[v][j];
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void gemv_pass(T (*acc)[B], const T (*w0)[16 / sizeof(T)], const T *const *wrow,
+                                          const int *kmax, const T *Xs, int nk, int k0, int kl) {
+  constexpr int VW = 16 / (int)sizeof(T), KS = 16 * VW;
+  const int kend = min(nk - k0, kGemvKX);
+  gemv_fma<T, B>(acc, w0, Xs, kl * VW);   // the first step's factor values came with the staging
+#pragma unroll 2
+  for (int s = 1; s * KS < kend; ++s) {
+    const int kk = s * KS + kl * VW;
+    T w[4][VW];
+    gemv_load<T, B>(w, wrow, kmax, k0 + kk);
+    gemv_fma<T, B>(acc, w, Xs, kk);
   }
 }
 
@@ -895,22 +920,40 @@ __device__ __forceinline__ void gemv_fwd_tile(const StageArgs &a, int tix, T *Xs
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[it][j] = T(0);
   for (int k0 = 0; k0 < J.K; k0 += kGemvKX) {
+    T w0[4][VW];
+    gemv_load<T, B>(w0, wrow, kmax, k0 + kl * VW);
     __syncthreads();
     gemv_stage_x<T, B, true>(Xs, a, J.in_row, rmap, J.K, k0);
     __syncthreads();
-    gemv_pass<T, B>(acc, wrow, kmax, Xs, J.K, k0, kl);
+    gemv_pass<T, B>(acc, w0, wrow, kmax, Xs, J.K, k0, kl);
   }
   gemv_reduce<T, B>(acc);
+  // epilogue: indices first, then the added rows, then the stores
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
   const int j = min(kl, a.nrhs - 1);
+  int r[4], orow[4];
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
-    const int r = min(gr[it], J.M - 1);
-    T v = pick_col<T, B>(acc[it], kl);
-    if (J.skel) v += src[(int64_t)(J.in_row + rmap[J.K + r]) * a.lds + j];
-    if (gr[it] < J.M && kl < a.nrhs) dst[out_row(a, J.out_row, r) * a.ldd + kl] = v;
+    r[it] = min(gr[it], J.M - 1);
+    orow[it] = a.rowmap ? a.rowmap[J.out_row + r[it]] : J.out_row + r[it];
   }
+  T v[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) v[it] = pick_col<T, B>(acc[it], kl);
+  if (J.skel) {
+    int srow[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) srow[it] = J.in_row + rmap[J.K + r[it]];
+    T x[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) x[it] = src[(int64_t)srow[it] * a.lds + j];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) v[it] += x[it];
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+    if (gr[it] < J.M && kl < a.nrhs) dst[(int64_t)orow[it] * a.ldd + kl] = v[it];
 }
 
 template <typename T, int B>
@@ -943,37 +986,56 @@ __device__ __forceinline__ void gemv_bwd_tile(const StageArgs &a, int tix, T *Xs
       kmax[it] = in ? C.ldwt - VW : 1 << 30;
     }
     for (int k0 = 0; k0 < C.M; k0 += kGemvKX) {
+      T w0[4][VW];
+      gemv_load<T, B>(w0, wrow, kmax, k0 + kl * VW);
       __syncthreads();
       gemv_stage_x<T, B, false>(Xs, a, C.g_row, nullptr, C.M, k0);
       __syncthreads();
-      gemv_pass<T, B>(acc, wrow, kmax, Xs, C.M, k0, kl);
+      gemv_pass<T, B>(acc, w0, wrow, kmax, Xs, C.M, k0, kl);
     }
   }
   gemv_reduce<T, B>(acc);
+  // epilogue: indices first, then the added rows (rows that take nothing from a
+  // consumer read its first gradient row and add zero), then the stores
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
   const int j = min(kl, a.nrhs - 1);
-  const int32_t *jm = J.map_off >= 0 ? a.maps + J.map_off : nullptr;
+  const bool two = J.nc > 1;
+  int r[4], prow[4], g[2][4];
+  bool add[2];
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int r = min(gr[it], J.K - 1);
-    T v = pick_col<T, B>(acc[it], kl);
-    int pr = r;
-    if (jm) {
-      pr = jm[r];
+  for (int it = 0; it < 4; ++it) r[it] = min(gr[it], J.K - 1);
+  if (J.map_off >= 0) {
+    const int32_t *jm = a.maps + J.map_off;
 #pragma unroll
-      for (int ci = 0; ci < 2; ++ci)
-        if (ci < J.nc) {
-          const int32_t g = jm[(ci + 1) * J.K + r];
-          if (g >= 0) v += src[(int64_t)(J.c[ci].g_row + g) * a.lds + j];
-        }
-    } else {
-#pragma unroll
-      for (int ci = 0; ci < 2; ++ci)
-        if (ci < J.nc && J.c[ci].wt_off < 0) v += src[(int64_t)(J.c[ci].g_row + r) * a.lds + j];
+    for (int it = 0; it < 4; ++it) {
+      prow[it] = jm[r[it]];
+      g[0][it] = jm[J.K + r[it]];
+      g[1][it] = jm[(two ? 2 : 1) * J.K + r[it]];
     }
-    if (gr[it] < J.K && kl < a.nrhs) dst[(int64_t)(J.out_row + pr) * a.ldd + kl] = v;
+    add[0] = true;
+    add[1] = two;
+  } else {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) prow[it] = g[0][it] = g[1][it] = r[it];
+    add[0] = J.c[0].wt_off < 0;
+    add[1] = two && J.c[1].wt_off < 0;
   }
+  T v[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) v[it] = pick_col<T, B>(acc[it], kl);
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {
+    if (!add[ci]) continue;
+    T x[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) x[it] = src[(int64_t)(J.c[ci].g_row + max(g[ci][it], 0)) * a.lds + j];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) v[it] += g[ci][it] >= 0 ? x[it] : T(0);
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+    if (gr[it] < J.K && kl < a.nrhs) dst[(int64_t)(J.out_row + prow[it]) * a.ldd + kl] = v[it];
 }
 
 template <typename T, bool FWD, int B>
