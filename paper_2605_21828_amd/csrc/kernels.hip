@@ -199,12 +199,17 @@ __device__ __forceinline__ void mma_chunk(typename Cfg<T>::acc_t (*acc)[BN / 16]
 // wait counts stay exact); the clamped repeats near the end are L2 hits and are
 // never multiplied.  Ends with a barrier, so a following call may restage the
 // buffers.
-template <typename T, int BN, int FM, bool FULL, bool MAP>
+template <typename T, int BN, int FM, bool FULL, bool MAP, bool TWO = false>
 __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16], const T *const *wrow, int nk,
                                            const StageArgs &a, int32_t base, const int32_t *rmap, int n0, T *Xs,
-                                           int tid, int lrow, int lg, int nact) {
+                                           int tid, int lrow, int lg, int nact, const T *const *wrow1 = nullptr,
+                                           int nk1 = 0, int32_t base1 = 0, int nact1 = 0) {
+  // TWO: a second reduction (the other consumer of a transposed job) follows the
+  // first in the same pipeline, so its first loads overlap the first one's last
+  // chunks; chunk c < nch0 belongs to the first, the rest to the second.
   typedef Tiling<T, BN> Tl;
-  const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
+  const int nch0 = (nk + Tl::KC - 1) / Tl::KC;
+  const int nchunk = nch0 + (TWO ? (nk1 + Tl::KC - 1) / Tl::KC : 0);
   if (nchunk <= 0) return;
   T w0[FM][Tl::KL], w1[FM][Tl::KL], w2[FM][Tl::KL], x0[Tl::XR], x1[Tl::XR];
   const int kx = tid % Tl::KC;
@@ -215,15 +220,17 @@ __device__ __forceinline__ void gemm_block(typename Cfg<T>::acc_t (*acc)[BN / 16
   // in flight.
   auto load_chunk = [&](T (*w)[Tl::KL], T *x, int c) {
     c = min(c, nchunk - 1);
-    load_x<T, BN, FULL, MAP>(x, a, base, nk, c * Tl::KC, n0, tid, mrow);
+    const bool sec = TWO && c >= nch0;
+    const int cl = sec ? c - nch0 : c;
+    load_x<T, BN, FULL, MAP>(x, a, sec ? base1 : base, sec ? nk1 : nk, cl * Tl::KC, n0, tid, mrow);
     if (MAP) mrow = rmap[min((c + 1) * Tl::KC + kx, nk - 1)];
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
+    for (int fm = 0; fm < FM; ++fm) load_w<T, BN>(w[fm], sec ? wrow1[fm] : wrow[fm], cl * Tl::KC, lg);
   };
   // factor chunk c lives in register set c mod 3, RHS chunk c in set c mod 2
   auto step = [&](T (*wc)[Tl::KL], const T *xn, T (*wl)[Tl::KL], T *xl, int c) {
     load_chunk(wl, xl, c + 2);
-    mma_chunk<T, BN, FM>(acc, wc, Xs + (c & 1) * Tl::XBUF, lrow, lg, nact);
+    mma_chunk<T, BN, FM>(acc, wc, Xs + (c & 1) * Tl::XBUF, lrow, lg, TWO && c >= nch0 ? nact1 : nact);
     store_x<T, BN>(Xs + ((c + 1) & 1) * Tl::XBUF, xn, tid);
     __syncthreads();
   };
@@ -429,21 +436,27 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = typename Cfg<T>::acc_t{0, 0, 0, 0};
+  // both consumers' reductions in one pipeline; a consumer with no row of the
+  // tile in its range (or an identity consumer) reduces over nothing
+  const T *pool = static_cast<const T *>(a.pool);
+  const T *wrow[2][FM];
+  int nk[2], na[2];
+  int32_t gb[2];
 #pragma unroll
   for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
-    if (ci >= J.nc) break;
     const Cons C = J.c[ci];
-    if (C.wt_off < 0 || C.hi <= tile.m0 || C.lo >= tile.m0 + 64 * FM) continue;   // no row of the tile reduces
-    const T *pool = static_cast<const T *>(a.pool);
-    const T *wrow[FM];
+    const bool on = ci < J.nc && C.wt_off >= 0 && C.hi > tile.m0 && C.lo < tile.m0 + 64 * FM;
+    nk[ci] = on ? C.M : 0;
+    gb[ci] = C.g_row;
+    na[ci] = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) {   // rows of W^T are columns of P
       const int r = rbase + fm * 16 + lrow;
-      wrow[fm] = r >= C.lo && r < C.hi ? pool + C.wt_off + (int64_t)(r - C.lo) * C.ldwt : pool;
+      wrow[ci][fm] = on && r >= C.lo && r < C.hi ? pool + C.wt_off + (int64_t)(r - C.lo) * C.ldwt : pool;
     }
-    const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
-    gemm_block<T, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
+  gemm_block<T, BN, FM, FULL, false, true>(acc, wrow[0], nk[0], a, gb[0], nullptr, n0, Xs, tid, lrow, lg, na[0],
+                                           wrow[1], nk[1], gb[1], na[1]);
   bwd_epilogue<T, BN, FM>(a, J, acc, rbase, n0, lane);
 }
 
@@ -586,26 +599,32 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
 // as gemm_block (no conditions in the loop body, tail peeled, final barrier).  Xs
 // holds 2 buffers per term: term t buffer j at Xs + (2 t + j) XBUF.  wrow[fm][t]:
 // term t of row fm.
-template <int NTERM, int BN, int FM, bool FULL, bool MAP>
+template <int NTERM, int BN, int FM, bool FULL, bool MAP, bool TWO = false>
 __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int nk,
                                               const StageArgs &a, int32_t base, const int32_t *rmap, int n0,
-                                              uint16_t *Xs, int tid, int lrow, int lg, int nact) {
+                                              uint16_t *Xs, int tid, int lrow, int lg, int nact,
+                                              const uint16_t *const (*wrow1)[3] = nullptr, int nk1 = 0,
+                                              int32_t base1 = 0, int nact1 = 0) {
   typedef TilingB<NTERM, BN> Tl;
-  const int nchunk = (nk + Tl::KC - 1) / Tl::KC;
+  const int nch0 = (nk + Tl::KC - 1) / Tl::KC;   // TWO: a second reduction follows in the same pipeline
+  const int nchunk = nch0 + (TWO ? (nk1 + Tl::KC - 1) / Tl::KC : 0);
   if (nchunk <= 0) return;
   uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
   float xB[Tl::XR];
   const int kx = 2 * (tid % 32);
   int mrow[2] = {MAP ? rmap[min(kx, nk - 1)] : 0, MAP ? rmap[min(kx + 1, nk - 1)] : 0};
   auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {  // same order as in gemm_block
-    load_x_bf<NTERM, BN, FULL, MAP>(xB, a, base, nk, c * Tl::KC, n0, tid, mrow);
+    const bool sec = TWO && c >= nch0;
+    const int cl = sec ? c - nch0 : c;
+    load_x_bf<NTERM, BN, FULL, MAP>(xB, a, sec ? base1 : base, sec ? nk1 : nk, cl * Tl::KC, n0, tid, mrow);
     if (MAP) {
       mrow[0] = rmap[min((c + 1) * Tl::KC + kx, nk - 1)];
       mrow[1] = rmap[min((c + 1) * Tl::KC + kx + 1, nk - 1)];
     }
 #pragma unroll
-    for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(w[fm], wrow[fm], c * Tl::KC, lg);
+    for (int fm = 0; fm < FM; ++fm) load_w_bf<NTERM, BN>(w[fm], sec ? wrow1[fm] : wrow[fm], cl * Tl::KC, lg);
   };
+  auto na_of = [&](int c) { return TWO && c >= nch0 ? nact1 : nact; };
   uint16_t *X0 = Xs, *X1 = Xs + Tl::XBUF;
   load_chunk(wA, 0);
   store_x_bf<NTERM, BN>(X0, xB, tid);
@@ -613,11 +632,11 @@ __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_
   int c = 0;
   for (; c + 2 < nchunk; c += 2) {
     load_chunk(wB, c + 1);
-    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, na_of(c));
     store_x_bf<NTERM, BN>(X1, xB, tid);
     __syncthreads();
     load_chunk(wA, c + 2);
-    mma_chunk_bf<NTERM, BN, FM>(acc, wB, X1, lrow, lg, nact);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wB, X1, lrow, lg, na_of(c + 1));
     store_x_bf<NTERM, BN>(X0, xB, tid);
     __syncthreads();
   }
@@ -625,7 +644,7 @@ __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_
   const bool two = c + 1 < nchunk;
   if (two) {
     load_chunk(wB, c + 1);
-    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, nact);
+    mma_chunk_bf<NTERM, BN, FM>(acc, wA, X0, lrow, lg, na_of(c));
     store_x_bf<NTERM, BN>(X1, xB, tid);
     __syncthreads();
 #pragma unroll
@@ -636,7 +655,7 @@ __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_
         wA[fm][t][1] = wB[fm][t][1];
       }
   }
-  mma_chunk_bf<NTERM, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, nact);
+  mma_chunk_bf<NTERM, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, na_of(two ? c + 1 : c));
   __syncthreads();
 }
 
@@ -689,23 +708,27 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
+  const uint16_t *wrow[2][FM][3];   // both consumers in one pipeline, as in bwd_tile
+  int nk[2], na[2];
+  int32_t gb[2];
 #pragma unroll
   for (int ci = 0; ci < 2; ++ci) {  // constant indices keep the job in registers
-    if (ci >= J.nc) break;
     const Cons C = J.c[ci];
-    if (C.wt_off < 0 || C.hi <= tile.m0 || C.lo >= tile.m0 + 64 * FM) continue;   // as in bwd_tile
-    const uint16_t *wrow[FM][3];
+    const bool on = ci < J.nc && C.wt_off >= 0 && C.hi > tile.m0 && C.lo < tile.m0 + 64 * FM;
+    nk[ci] = on ? C.M : 0;
+    gb[ci] = C.g_row;
+    na[ci] = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) {
       const int r = rbase + fm * 16 + lrow;
-      const int64_t roff = r >= C.lo && r < C.hi ? C.wt_off + (int64_t)(r - C.lo) * C.ldwt : 0;
-      wrow[fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
-      wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
-      wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
+      const int64_t roff = on && r >= C.lo && r < C.hi ? C.wt_off + (int64_t)(r - C.lo) * C.ldwt : 0;
+      wrow[ci][fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
+      wrow[ci][fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
+      wrow[ci][fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
     }
-    const int na = rbase < C.hi && rbase + 16 * FM > C.lo ? nact : 0;
-    gemm_block_bf<NTERM, BN, FM, FULL, false>(acc, wrow, C.M, a, C.g_row, nullptr, n0, Xs, tid, lrow, lg, na);
   }
+  gemm_block_bf<NTERM, BN, FM, FULL, false, true>(acc, wrow[0], nk[0], a, gb[0], nullptr, n0, Xs, tid, lrow, lg,
+                                                  na[0], wrow[1], nk[1], gb[1], na[1]);
   bwd_epilogue<float, BN, FM>(a, J, acc, rbase, n0, lane);
 }
 
