@@ -50,6 +50,23 @@ def measured_traffic(workload):
     return d["fwd_per_dispatch"]["hbm_bytes"]
 
 
+def measured_mfma_busy(workload):
+    """MFMA busy percentage of the forward FP32 stage launches from the committed
+    rocprofv3 MfmaUtil summary, or None when the kernels have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "mfma_util_%s.json" % workload)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        with open(os.path.join(ROOT, "paper_2605_21828_amd", "csrc", "kernels.hip"), "rb") as f:
+            cur = hashlib.sha1(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if d.get("kernels_hip_sha1") != cur:
+        return None
+    return d["fwd"]["mfma_busy_pct"]
+
+
 # MI355X spec-sheet peaks: dense MFMA TFLOP/s per arithmetic type and HBM GB/s.
 MFMA_PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
 HBM_PEAK = 8000.0
@@ -702,6 +719,7 @@ def main():
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per launch",
+                     "mfma_busy_pct_counter": measured_mfma_busy(args.workload),
                      "alg_bytes_per_launch": alg_bytes32 / launches,
                      # level vectors written by one stage and read by the next: not
                      # algorithmic (intermediate), reported beside it
