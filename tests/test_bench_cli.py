@@ -1,0 +1,38 @@
+"""Host-side checks of the benchmark script: the one-GPU contract and its roofline arithmetic."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_roofline_picks_the_binding_roof():
+    # FP32 at 64 RHS: 2*F*64 flops against 4*F bytes is above the FP32 ridge -> MFMA-bound
+    F, n, m = 10**8, 65536, 16384
+    r = bench.roofline_for("f32", F, n, m, 64, apply_ms=1.0, launches=11)
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert abs(r["achieved"] - 2.0 * F * 64 / 1e-3 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 157.3) < 1e-12
+    # one RHS: bytes dominate -> HBM-bound, algorithmic bytes = 4 F + 4 (n + m)
+    r1 = bench.roofline_for("f32", F, n, m, 1, apply_ms=1.0, launches=11)
+    assert r1["bound"] == "hbm"
+    assert abs(r1["achieved"] - (4.0 * F + 4.0 * (n + m)) / 1e-3 / 1e9) < 1e-6
+    # split products multiply the executed flops
+    r3 = bench.roofline_for("bf16x3", F, n, m, 256, apply_ms=1.0, launches=11)
+    assert r3["bound"] == "mfma" and abs(r3["achieved"] - 6 * 2.0 * F * 256 / 1e-3 / 1e12) < 1e-6
+
+
+def test_level_bytes_counts_every_level_vector_twice():
+    fs = {"rank": np.array([[1, 2], [3, 4]], dtype=np.int32)}
+    assert bench.level_bytes(fs, 8, 4) == 2.0 * 10 * 8 * 4
