@@ -14,6 +14,8 @@
 // Factor blocks are stored twice: row-major W (M x K, row stride ldw) for the
 // forward stages and row-major W^T (K x M, row stride ldwt) for the transposed
 // stages, so both directions stream factor rows with the same access pattern.
+// A block with the column-ID form P = [I T] Pi^T keeps only T in the forward
+// pool and only the rows of T^T in the transposed pool (see FwdJob and BwdJob).
 #pragma once
 #include <stdint.h>
 
