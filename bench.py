@@ -546,6 +546,83 @@ def bench_inverse(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_latency(args):
+    """Uniform 64 x 64 grid, 1024 modes, one RHS: a latency-bound apply whose
+    factors stay in L2/MALL.  Times the FP64 (and FP32) synthesis and analysis
+    eagerly and as HIP graph replays (torch CUDA graphs capture the library's
+    kernel launches on the capturing stream), and checks FP64 against the oracle
+    and the inverse DFT."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+
+    w = wl.WORKLOADS["grid64"]
+    pts = wl.points_for(w)
+    fs, _ = fio.fourier_factors(pts, w["m"], w["leaf"], w["tol"], workers=args.workers, cache=args.cache)
+    n, m, b = w["n"], w["m"], w["nrhs"]
+    c_host = wl.coefficients(w["wid"], m, b)
+    f_host = wl.values(w["wid"], n, b)
+    dev = torch.device("cuda:0")
+    reps = max(200, args.steps)
+    rec, outs = {}, {}
+    for prec in ("f64", "f32"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        p = Plan(fs, prec, max_nrhs=b, device=dev)
+        x = torch.tensor(c_host, dtype=dt, device=dev)
+        fv = torch.tensor(f_host, dtype=dt, device=dev)
+        y = torch.empty((n, b), dtype=dt, device=dev)
+        g = torch.empty((m, b), dtype=dt, device=dev)
+        for _ in range(max(3, args.warmup)):
+            p.apply(x, out=y)
+            p.apply_t(fv, out=g)
+        torch.cuda.synchronize()
+        eager_f = event_time(lambda: p.apply(x, out=y), reps, torch)
+        eager_b = event_time(lambda: p.apply_t(fv, out=g), reps, torch)
+        graphs = []
+        for fn in (lambda: p.apply(x, out=y), lambda: p.apply_t(fv, out=g)):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                fn()
+            graphs.append(gr)
+        graph_f = event_time(graphs[0].replay, reps, torch)
+        graph_b = event_time(graphs[1].replay, reps, torch)
+        torch.cuda.synchronize()
+        outs[prec] = (y.double().cpu().numpy(), g.double().cpu().numpy())
+        rec[prec] = {"apply_us": eager_f * 1e3, "apply_transpose_us": eager_b * 1e3,
+                     "graph_apply_us": graph_f * 1e3, "graph_apply_transpose_us": graph_b * 1e3}
+        log("%s: apply %.1f us (graph %.1f), transpose %.1f us (graph %.1f)" % (
+            prec, eager_f * 1e3, graph_f * 1e3, eager_b * 1e3, graph_b * 1e3))
+    checks = None
+    if not args.no_cpu_baseline:
+        from oracle import butterfly as ob
+        from oracle import dense as od
+        from oracle import modes as om
+        md = om.fourier_modes(m)
+        y64, g64 = outs["f64"]
+        checks = {"f64_vs_oracle_butterfly": od.rel_err_cols(y64, ob.apply(fs, c_host))[0],
+                  "f64_transpose_vs_oracle_butterfly": od.rel_err_cols(g64, ob.apply_transpose(fs, f_host))[0],
+                  "f64_vs_inverse_dft": od.rel_err_cols(y64, om.grid_synthesis_ifft2(w["N"], md, c_host))[0],
+                  "f32_vs_inverse_dft": od.rel_err_cols(outs["f32"][0], om.grid_synthesis_ifft2(w["N"], md, c_host))[0]}
+    F = fio.stored_entries(fs)
+    # the faster of eager launches and graph replay (graph replay measured slower here)
+    t = min(rec["f64"]["apply_us"], rec["f64"]["graph_apply_us"])
+    plan_f = Plan(fs, "f64", max_nrhs=b, device=dev)
+    res = {
+        "metric": "FP64 synthesis latency (one RHS)",
+        "value": t, "unit": "us", "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": t * 1e-3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "grid64", "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
+                   "L": int(fs["L"]), "step": "one apply"},
+        "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2),
+                         note="latency-bound: the factors are L2/MALL-resident; reported, not a target"),
+        "cpu_baseline": None,
+        "extra": {"stored_factor_entries": F, "precisions": rec, "checks": checks},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_copy(args):
     """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
     import torch
@@ -581,6 +658,8 @@ def main():
         return bench_batched(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "grid64":
+        return bench_latency(args)
     if args.workload == "inverse_sphere40962":
         return bench_inverse(args)
     if args.workload in ("lsq262144", "lsq131072"):
