@@ -1156,6 +1156,54 @@ int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *per
   return (int)hipGetLastError();
 }
 
+// Sum of row copies: dst[r] = the C rows src[inv[r C + k]] summed pairwise in a
+// balanced tree over k (left to right within each pair), the order in which the
+// transposed identity levels it replaces add them.  slot[d] holds the pending
+// left operand of tree depth d; C is a power of two, at most 2^15.
+template <typename T>
+__global__ __launch_bounds__(kNT) void fold_sum_kernel(const T *src, int64_t lds, const int32_t *inv, int C,
+                                                       int64_t rows, T *dst, int64_t ldd, int nrhs) {
+  const int64_t total = rows * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (int64_t)gridDim.x * kNT) {
+    const int64_t r = e / nrhs;
+    const int j = (int)(e % nrhs);
+    T slot[16] = {};
+    for (int k = 0; k < C; ++k) {
+      T carry = src[(int64_t)inv[r * C + k] * lds + j];
+#pragma unroll
+      for (int d = 0; d < 16; ++d) {
+        if ((k >> d) & 1) {
+          carry = slot[d] + carry;
+        } else {
+          slot[d] = carry;
+          break;
+        }
+      }
+    }
+    int depth = 0;
+    while ((1 << depth) < C) ++depth;
+    T v = slot[0];
+#pragma unroll
+    for (int d = 1; d < 16; ++d) v = d == depth ? slot[d] : v;
+    dst[r * ldd + j] = v;
+  }
+}
+
+int launch_fold_sum(int esz, const void *src, int64_t lds, const int32_t *inv, int C, int64_t rows, void *dst,
+                    int64_t ldd, int nrhs, void *stream) {
+  const int64_t total = rows * nrhs;
+  if (total == 0) return 0;
+  if (C < 1 || C > (1 << 15) || (C & (C - 1))) return (int)hipErrorInvalidValue;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + kNT - 1) / kNT, 8192);
+  if (esz == 8)
+    hipLaunchKernelGGL((fold_sum_kernel<double>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const double *>(src), lds, inv, C, rows, static_cast<double *>(dst), ldd, nrhs);
+  else
+    hipLaunchKernelGGL((fold_sum_kernel<float>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const float *>(src), lds, inv, C, rows, static_cast<float *>(dst), ldd, nrhs);
+  return (int)hipGetLastError();
+}
+
 // Row scaling: dst[r] = s[r] * src[r] for r < rows (rows of nrhs elements);
 // dst may equal src (same ld).  Carries the diagonal of the scaled applies.
 

@@ -50,6 +50,8 @@ float bf16_to_f32(uint16_t h) {
 struct StageDesc {
   int kind;   // 0: level 0 (reads c), 1: transfer level, 2: final (writes f through perm_x)
   int level;
+  bool skip = false;    // forward only: an all-identity level folded into the first later stage
+  bool edge = false;    // forward only: the first stage after the folded levels (reads c)
   int64_t fjob0, nfjob, bjob0, nbjob;
   int64_t ftile0[2], nftile[2], btile0[2], nbtile[2];  // tile lists for 64- and 128-row tiles
 };
@@ -72,6 +74,10 @@ struct bfmht_plan {
   int64_t stored_fwd = 0;          // factor entries of the forward pool (compact blocks store T only)
   std::vector<int32_t> maps;       // forward jobs' row-index table
   int64_t off_maps = 0;
+  int nfold = 0;                   // leading all-identity levels (folded, see plan creation)
+  int64_t fold_copies = 0;         // copies of each row of c at level nfold-1
+  std::vector<int32_t> fold_inv;   // per row of c, its level nfold-1 rows in space-node order
+  int64_t off_fold = 0;
   int64_t off_pool[3] = {0, 0, 0};   // forward pool, one region per term
   int64_t off_tpool[3] = {0, 0, 0};  // transposed pool
   int64_t off_fjobs = 0, off_bjobs = 0, off_tiles = 0, off_perm = 0, dev_bytes = 0;
@@ -462,6 +468,75 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
     p->stages.push_back(s);
   }
   p->tpool_elems = tpool;
+
+  // Leading all-identity levels move rows without arithmetic in the forward
+  // direction: level l's output repeats rows of level l-1's (each space node at
+  // level l takes a copy of its frequency children).  They are folded into the
+  // first later stage e, whose forward jobs read c through the composed row map
+  // pi (level e-1 row -> row of c), so no copy stage is launched for them.
+  // Identity jobs of stage e become row-gather jobs (a compact job with nothing
+  // to reduce and every row a skeleton row).  The transposed direction keeps its
+  // stages: there the copies of one row of c are summed.
+  int nfold = 0;
+  while (nfold <= L) {
+    bool all = true;
+    for (int64_t q = 0; q < nb && all; ++q) all = f->ident[nfold * nb + q] != 0;
+    if (!all) break;
+    ++nfold;
+  }
+  if (nfold > 0) {
+    // pi over the rows of level nfold-1
+    std::vector<int64_t> pi((size_t)off[0][nb]);
+    for (int64_t j = 0; j < nb; ++j)
+      for (int64_t t = 0; t < f->rank[j]; ++t) pi[off[0][j] + t] = f->koff[j] + t;
+    for (int lvl = 1; lvl < nfold; ++lvl) {
+      std::vector<int64_t> nx((size_t)off[lvl][nb]);
+      const int64_t nf = 1ll << (L - lvl);
+      for (int64_t q = 0; q < nb; ++q) {
+        const int64_t i = q / nf, j = q % nf, q1 = (i >> 1) * 2 * nf + 2 * j;
+        for (int64_t t = 0; t < f->rank[lvl * nb + q]; ++t) nx[off[lvl][q] + t] = pi[off[lvl - 1][q1] + t];
+      }
+      pi.swap(nx);
+    }
+    for (int k = 0; k < nfold; ++k) p->stages[k].skip = true;
+    // Transposed direction: the folded levels sum the copies of each row of c,
+    // pairwise over the space nodes (a balanced tree).  One gather-sum over the
+    // level nfold-1 rows replaces those stages in a single apply.
+    const int64_t C = 1ll << (nfold - 1), rows = off[nfold - 1][nb];
+    if (rows == f->m * C) {
+      std::vector<int32_t> cnt((size_t)f->m, 0);
+      p->fold_inv.assign((size_t)rows, -1);
+      bool ok = true;
+      for (int64_t r = 0; r < rows && ok; ++r) {
+        const int64_t cr = pi[r];
+        ok = cr >= 0 && cr < f->m && cnt[cr] < C;
+        if (ok) p->fold_inv[(size_t)(cr * C + cnt[cr]++)] = (int32_t)r;
+      }
+      if (ok) {
+        p->nfold = nfold;
+        p->fold_copies = C;
+      } else {
+        std::vector<int32_t>().swap(p->fold_inv);
+      }
+    }
+    StageDesc &e = p->stages[nfold];
+    e.edge = true;
+    for (int64_t t = e.fjob0; t < e.fjob0 + e.nfjob; ++t) {
+      FwdJob &J = fj[t];
+      if (J.w_off < 0) {   // identity: y rows = x rows, as skeleton copies
+        J.map_off = (int32_t)p->maps.size();
+        for (int32_t r = 0; r < J.M; ++r) p->maps.push_back((int32_t)pi[J.in_row + r]);
+        J.w_off = 0;
+        J.K = 0;
+        J.ldw = 0;
+        J.skel = 1;
+      } else {
+        const int32_t nidx = J.K + (J.skel ? J.M : 0);
+        for (int32_t u = 0; u < nidx; ++u) p->maps[J.map_off + u] = (int32_t)pi[J.in_row + p->maps[J.map_off + u]];
+      }
+      J.in_row = 0;
+    }
+  }
   for (auto &s : p->stages) {
     add_ftiles(s);
     add_btiles(s);
@@ -493,6 +568,8 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   cur = align_up(cur + f->n * 4, 256);
   p->off_maps = cur;
   cur = align_up(cur + (int64_t)p->maps.size() * 4, 256);
+  p->off_fold = cur;
+  cur = align_up(cur + (int64_t)p->fold_inv.size() * 4, 256);
   p->dev_bytes = std::max<int64_t>(cur, 256);
 
   try {
@@ -531,6 +608,8 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   }
   if (!p->maps.empty()) std::memcpy(S + p->off_maps, p->maps.data(), p->maps.size() * 4);
   std::vector<int32_t>().swap(p->maps);
+  if (!p->fold_inv.empty()) std::memcpy(S + p->off_fold, p->fold_inv.data(), p->fold_inv.size() * 4);
+  std::vector<int32_t>().swap(p->fold_inv);
   if (!fj.empty()) std::memcpy(S + p->off_fjobs, fj.data(), fj.size() * sizeof(FwdJob));
   if (!bj.empty()) std::memcpy(S + p->off_bjobs, bj.data(), bj.size() * sizeof(BwdJob));
   if (!tiles.empty()) std::memcpy(S + p->off_tiles, tiles.data(), tiles.size() * sizeof(Tile));
@@ -621,7 +700,7 @@ StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, int rows, 
   a.nrhs = nrhs;
   if (fwd) {
     // stage l reads level l-1 (or c) and writes level l (or f)
-    if (s.kind == 0) { a.src = in; a.lds = ldin; } else { a.src = buf[(s.level - 1) & 1]; a.lds = nrhs; }
+    if (s.kind == 0 || s.edge) { a.src = in; a.lds = ldin; } else { a.src = buf[(s.level - 1) & 1]; a.lds = nrhs; }
     if (s.kind == 2) { a.dst = out; a.ldd = ldout; } else { a.dst = buf[s.level & 1]; a.ldd = nrhs; }
   } else {
     // the transposed stage l reads level l (the leaf stage: f gathered into tree
@@ -665,6 +744,7 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
   for (int k = 0; k < S; ++k) {
     const int si = fwd ? k : S - 1 - k;
     const StageDesc &s = p->stages[si];
+    if (fwd ? s.skip : si < p->nfold) continue;   // folded identity levels
     const int d = fwd ? 0 : 1;
     if (gemv) {   // few right-hand sides: vector FMAs over the 64-row tiles
       StageArgs a = stage_io(p, s, fwd, kTileRows, in, ldin, out, ldout, nrhs, buf);
@@ -676,6 +756,12 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
     StageArgs a = stage_io(p, s, fwd, rows, in, ldin, out, ldout, nrhs, buf);
     const int e = fwd ? launch_fwd_stage(p->prec, a, rows, cols, stream) : launch_bwd_stage(p->prec, a, rows, cols, stream);
     if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
+  }
+  if (!fwd && p->nfold > 0) {   // sum the copies of each row of c (the folded transposed levels)
+    const int e = launch_fold_sum((int)p->esz, buf[(p->nfold - 1) & 1], nrhs,
+                                  reinterpret_cast<const int32_t *>(p->dev + p->off_fold), (int)p->fold_copies, p->m,
+                                  out, ldout, nrhs, stream);
+    if (e) return fail(BFMHT_EHIP, std::string("fold launch: ") + hipGetErrorString((hipError_t)e));
   }
   return BFMHT_OK;
 }
@@ -877,6 +963,10 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
     for (int k = 0; k < S; ++k) {
       const int si = fwd ? k : S - 1 - k;
       Segment sg{};
+      if (fwd && p->stages[si].skip) {   // folded identity level: an empty segment keeps the stage positions aligned
+        per[i].push_back(sg);
+        continue;
+      }
       const int d = fwd ? 0 : 1;
       const int rows = gemv ? kTileRows : p->rows[d][si];
       sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);

@@ -189,3 +189,27 @@ def test_autotune_sets_widths_and_keeps_results(gpu, instances, tmp_path):
     xs = [_t(np.random.default_rng(13).standard_normal((pl.m, max(1, c[5]))), _dt("f32")) for pl, c in zip(plans, CASES)]
     choice, ms = autotune.tune_batch(Batch(plans), xs, reps=2)
     assert len(choice) == len(plans) and ms > 0
+
+
+@pytest.mark.parametrize("nrhs", [3, 16])
+def test_folded_identity_levels_match_unfolded_bitwise(gpu, nrhs):
+    """The single apply folds leading all-identity levels (forward: rows read
+    through the composed map; transposed: one pairwise gather-sum of the row
+    copies); the batched apply runs those stages transposed one by one.  The
+    sums happen in the same order, so results agree bitwise."""
+    import torch
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    w = wl.WORKLOADS["grid64"]
+    fs, _ = fio.fourier_factors(wl.points_for(w), w["m"], w["leaf"], w["tol"], workers=8, cache=False)
+    assert fs["ident"][0].all() and fs["ident"][1].all()
+    rng = np.random.default_rng(9)
+    for prec in ("f64", "f32"):
+        p = Plan(fs, prec, max_nrhs=nrhs)
+        f = _t(rng.standard_normal((int(fs["n"]), nrhs)), _dt(prec))
+        c = _t(rng.standard_normal((int(fs["m"]), nrhs)), _dt(prec))
+        g_single, y_single = _np(p.apply_t(f)), _np(p.apply(c))
+        g_batch = _np(Batch([p]).run([f], transpose=True)[0])
+        assert np.array_equal(g_single, g_batch), prec
+        tol = 1e-12 if prec == "f64" else 1e-5
+        assert od.rel_err_cols(g_single, ob.apply_transpose(fs, f.double().cpu().numpy()))[0] <= tol
+        assert od.rel_err_cols(y_single, ob.apply(fs, c.double().cpu().numpy()))[0] <= tol
