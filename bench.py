@@ -100,10 +100,21 @@ def roofline_for(prec, F, n, m, b, apply_ms, launches):
     return r
 
 
+def folded_levels(fs):
+    """Leading all-identity levels, which the forward apply folds into its first
+    stage (no launch of their own)."""
+    ident, L = np.asarray(fs["ident"]), int(fs["L"])
+    k = 0
+    while k <= L and ident[k].all():
+        k += 1
+    return k
+
+
 def level_bytes(fs, b, s_x):
-    """Implementation bytes of one apply: every level vector (sum of the ranks of
-    a level, b columns) written once and read once."""
-    return 2.0 * float(np.asarray(fs["rank"], dtype=np.int64).sum()) * b * s_x
+    """Implementation bytes of one forward apply: every level vector it writes
+    (sum of the ranks of a level, b columns; folded levels have none) written
+    once and read once."""
+    return 2.0 * float(np.asarray(fs["rank"], dtype=np.int64)[folded_levels(fs):].sum()) * b * s_x
 
 
 def _blas_threads():
@@ -337,7 +348,7 @@ def bench_sphere(args):
     else:
         base = None
     t_main = rec[main]["apply_ms"]
-    roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=int(fs["L"]) + 2)
+    roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=int(fs["L"]) + 2 - folded_levels(fs))
     res = {
         "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
         "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
@@ -455,7 +466,7 @@ def bench_lsq(args):
     reps = 5
     ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
     ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)
-    roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2)
+    roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2 - folded_levels(fs))
     base, acc = None, {}
     if not args.no_cpu_baseline:
         log("oracle checks: finite differences and dense gradient")
@@ -522,7 +533,8 @@ def bench_inverse(args):
     c_np = c.double().cpu().numpy()
     # algorithmic bytes of one step: both applies' factor bytes (the forward one
     # reads the compact ID blocks) plus their inputs and outputs
-    launches = 2 * (int(fs["L"]) + 2)
+    # stage launches of both applies, the input gather and copy sum, and the six vector kernels
+    launches = 2 * (int(fs["L"]) + 2 - folded_levels(fs)) + 2 + 6
     step_bytes = (FACTOR_BYTES[prec] * (p.stored_fwd + p.stored_t)
                   + 2 * (8 if prec == "f64" else 4) * (n + m) * b)
     achieved = step_bytes / (per_iter * 1e-3) / 1e9
@@ -615,7 +627,7 @@ def bench_latency(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "grid64", "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
                    "L": int(fs["L"]), "step": "one apply"},
-        "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2),
+        "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2 - folded_levels(fs)),
                          note="latency-bound: the factors are L2/MALL-resident; reported, not a target"),
         "cpu_baseline": None,
         "extra": {"stored_factor_entries": F, "precisions": rec, "checks": checks},
@@ -717,7 +729,7 @@ def main():
     reps = max(args.steps, 5)
     ms_fwd = event_time(lambda: p32.apply(c32, out=y32), reps, torch)
     ms_bwd = event_time(lambda: p32.apply_t(f32, out=g32), reps, torch)
-    launches = int(fs["L"]) + 2   # stage-0, L transfer levels, final stage
+    launches = int(fs["L"]) + 2 - folded_levels(fs)   # stage-0, L transfer levels, final stage, less the folded ones
     # the forward apply reads the compact ID blocks (T only): its algorithmic
     # factor entries are the forward pool's, not the full factor count F
     F_fwd = p32.stored_fwd
