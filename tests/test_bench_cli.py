@@ -34,5 +34,10 @@ def test_roofline_picks_the_binding_roof():
 
 
 def test_level_bytes_counts_every_level_vector_twice():
-    fs = {"rank": np.array([[1, 2], [3, 4]], dtype=np.int32)}
+    fs = {"L": 1, "rank": np.array([[1, 2], [3, 4]], dtype=np.int32), "ident": np.zeros((2, 2), np.uint8)}
+    assert bench.folded_levels(fs) == 0
     assert bench.level_bytes(fs, 8, 4) == 2.0 * 10 * 8 * 4
+    # a leading all-identity level is folded: it has no level vector of its own
+    fs["ident"][0] = 1
+    assert bench.folded_levels(fs) == 1
+    assert bench.level_bytes(fs, 8, 4) == 2.0 * 7 * 8 * 4
