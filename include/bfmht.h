@@ -45,7 +45,9 @@ typedef struct bfmht_plan bfmht_plan;
 
 /* Arithmetic of the apply.  F64: factors, level vectors and I/O in double
  * (the plain baseline).  F32: factors and vectors in float, FP32 MFMA with
- * FP32 accumulation.  BF16X2 / BF16X3: factors pre-split at upload into 2 / 3
+ * FP32 accumulation.  F64 and F32 applies with at most 4 right-hand sides use
+ * vector FMAs instead of MFMA tiles (same jobs, same sums per output up to the
+ * order of the reduction).  BF16X2 / BF16X3: factors pre-split at upload into 2 / 3
  * bfloat16 terms (hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo),
  * round to nearest even), activations split the same way per tile, BF16 MFMA
  * products hi*hi + hi*lo + lo*hi (X2) or the six products whose term indices
@@ -187,7 +189,9 @@ bfmht_status bfmht_lsqr(const bfmht_plan *plan, const void *f, int64_t ldf, void
 int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
 
 /* Number of stages of one apply: L + 2 (level 0, the L transfer levels, the
- * leaf stage), numbered in forward order; -1 for NULL. */
+ * leaf stage), numbered in forward order; -1 for NULL.  Leading levels whose
+ * blocks are all identities are folded into the next stage by single applies
+ * (their tile shapes then have no effect). */
 int32_t bfmht_plan_num_stages(const bfmht_plan *plan);
 
 /* Tile shape of one stage of the forward (transpose = 0) or transposed
@@ -210,10 +214,11 @@ int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t co
  * nrhs[i] == 0 are skipped.  All plans must be uploaded and share one
  * precision.  Launch k runs the k-th stage of every instance at once (one work
  * item per output tile of each instance), so the number of launches is the
- * largest stage count in the batch, not the sum over instances.  ws: device
- * workspace, 256-byte aligned, at least bfmht_batched_workspace_bytes; it
- * holds the per-call tables (copied from host memory on `stream`) and each
- * instance's level buffers, so calls that overlap on one workspace race. */
+ * largest stage count in the batch, not the sum over instances (one launch per
+ * stage position and kernel shape; the per-stage segment tables travel as
+ * launch arguments).  ws: device workspace, 256-byte aligned, at least
+ * bfmht_batched_workspace_bytes; it holds each instance's level buffers, so
+ * calls that overlap on one workspace race. */
 bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
                                  const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
                                  int32_t transpose, void *ws, int64_t ws_bytes, void *stream);
