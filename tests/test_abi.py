@@ -184,3 +184,25 @@ def test_plan_create_ex_rejects_unknown_flags(good):
         B.bfmht_plan_create_ex(good, B.F32, 1, 2)
     assert e.value.status == B.EINVAL
     assert B.bfmht_plan_stored_entries(None, 0) == -1
+
+
+def test_fourier_factor_set_is_applied_in_compact_form():
+    """Factor sets from the builder keep exact unit skeleton columns, so every
+    non-identity transfer and level-0 block is compact in both directions."""
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.factor import io as fio
+    w = wl.WORKLOADS["grid64"]
+    fs, _ = fio.fourier_factors(wl.points_for(w), w["m"], w["leaf"], w["tol"], workers=1, cache=False)
+    full = int(fs["P"].size + fs["U"].size)
+    save = _id_saving(fs)
+    h = B.bfmht_plan_create_ex(fs, B.F64, 1, 0)
+    try:
+        assert save > 0
+        assert B.bfmht_plan_stored_entries(h, False) == B.bfmht_plan_stored_entries(h, True) == full - save
+    finally:
+        B.bfmht_plan_destroy(h)
+    # every stored transfer/level-0 block qualified
+    L, nb = int(fs["L"]), 1 << int(fs["L"])
+    n_blocks = sum(1 for lvl in range(L + 1) for q in range(nb)
+                   if not fs["ident"][lvl, q] and fs["P_off"][lvl, q] >= 0 and 0 < fs["rank"][lvl, q])
+    assert n_blocks > 0
