@@ -201,8 +201,22 @@ def test_fourier_factor_set_is_applied_in_compact_form():
         assert B.bfmht_plan_stored_entries(h, False) == B.bfmht_plan_stored_entries(h, True) == full - save
     finally:
         B.bfmht_plan_destroy(h)
-    # every stored transfer/level-0 block qualified
+    # every stored transfer/level-0 block with 0 < rank < inputs has the ID form:
+    # its saving is rank^2, so the total saving is the sum of rank^2 over them
     L, nb = int(fs["L"]), 1 << int(fs["L"])
-    n_blocks = sum(1 for lvl in range(L + 1) for q in range(nb)
-                   if not fs["ident"][lvl, q] and fs["P_off"][lvl, q] >= 0 and 0 < fs["rank"][lvl, q])
-    assert n_blocks > 0
+    expect = 0
+    for lvl in range(L + 1):
+        nf = 1 << (L - lvl)
+        for q in range(nb):
+            if fs["ident"][lvl, q] or fs["P_off"][lvl, q] < 0:
+                continue
+            r = int(fs["rank"][lvl, q])
+            if lvl == 0:
+                k = int(fs["koff"][q + 1] - fs["koff"][q])
+            else:
+                i, j = divmod(q, nf)
+                q1 = (i >> 1) * 2 * nf + 2 * j
+                k = int(fs["rank"][lvl - 1, q1] + fs["rank"][lvl - 1, q1 + 1])
+            if 0 < r < k:
+                expect += r * r
+    assert save == expect
