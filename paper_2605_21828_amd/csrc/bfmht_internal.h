@@ -114,11 +114,11 @@ constexpr int kGemvMaxRhs = 4;
 int launch_gemv_stage(int prec, bool fwd, const StageArgs &a, void *stream);
 int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
 
-// dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).
-// dst[r] = sum over the C copies k of src[inv[r C + k]] (rows of nrhs elements),
-// as a balanced pairwise tree in copy order; C a power of two.
+// dst[r] = sum over the C copies k of src[inv[r C + k]] (rows of nrhs elements of
+// esz bytes), as a balanced pairwise tree in copy order; C a power of two.
 int launch_fold_sum(int esz, const void *src, int64_t lds, const int32_t *inv, int C, int64_t rows, void *dst,
                     int64_t ldd, int nrhs, void *stream);
+// dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).
 int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *perm, int64_t n, void *dst, int64_t ldd,
                        int nrhs, void *stream);
 
@@ -163,8 +163,8 @@ struct SegPack {
 };
 static_assert(sizeof(SegPack) <= 4096, "launch arguments are limited to 4 KB");
 
-// One launch over `items` work items of the pack's segments (item0 relative to the pack).
-// One batched launch of segments that share the direction and the tile shape (bn x 64 fm).
+// One launch over `items` work items of the pack's segments (item0 relative to the
+// pack); the segments share the direction and the tile shape (bn x 64 fm).
 int launch_batched_stage(int prec, bool fwd, int bn, int fm, const SegPack &pack, int64_t items, void *stream);
 // One batched launch of few-RHS segments (each nrhs <= b, b in {1, 2, 4}) on the vector-FMA kernel.
 int launch_batched_gemv(int prec, bool fwd, int b, const SegPack &pack, int64_t items, void *stream);
