@@ -101,8 +101,9 @@ typedef struct {
 
 /* Validate the factor set and build the device layout for one precision.
  * On success *plan owns host metadata (stage tables, converted factors staged
- * for upload); on failure *plan is set to NULL.  max_nrhs >= 1 bounds the nrhs
- * of later applies (it sizes nothing on the device; workspace is per call). */
+ * for upload); on failure *plan is set to NULL.  max_nrhs >= 1 records the
+ * largest nrhs the caller means to use; it sizes nothing (workspace is per
+ * call), and applies with more columns are accepted. */
 bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precision prec,
                                int32_t max_nrhs, bfmht_plan **plan);
 

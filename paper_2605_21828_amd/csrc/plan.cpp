@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -184,18 +185,16 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
   return bfmht_plan_create_ex(f, prec, max_nrhs, 0, out);
 }
 
-bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs, int32_t flags,
-                                  bfmht_plan **out) {
-  if (!out) return fail(BFMHT_EINVAL, "plan output pointer is NULL");
-  if (flags & ~BFMHT_PLAN_FULL_BLOCKS) return fail(BFMHT_EINVAL, "unknown plan flags");
-  const bool compact_ids = (flags & BFMHT_PLAN_FULL_BLOCKS) == 0;
-  *out = nullptr;
-  if (prec < BFMHT_F64 || prec > BFMHT_BF16X3) return fail(BFMHT_EINVAL, "unknown precision");
-  if (max_nrhs < 1) return fail(BFMHT_EINVAL, "max_nrhs must be >= 1");
-  bfmht_status st = validate(f);
-  if (st != BFMHT_OK) return st;
+}  // extern "C"
 
-  bfmht_plan *p = new bfmht_plan();
+namespace {
+
+// Body of bfmht_plan_create_ex after argument checks; may throw std::bad_alloc
+// (the caller turns that into a status).  *out is set only on success.
+bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs, bool compact_ids,
+                        bfmht_plan **out) {
+  std::unique_ptr<bfmht_plan> owner(new bfmht_plan());
+  bfmht_plan *p = owner.get();
   p->prec = prec;
   p->n = f->n;
   p->m = f->m;
@@ -214,7 +213,6 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
     for (int64_t q = 0; q < nb; ++q) off[lvl][q + 1] = off[lvl][q] + f->rank[lvl * nb + q];
     p->level_rows[lvl] = off[lvl][nb];
     if (off[lvl][nb] >= (1ll << 31)) {
-      delete p;
       return fail(BFMHT_EINVAL, "level vector exceeds 2^31 rows");
     }
     p->max_rows = std::max(p->max_rows, off[lvl][nb]);
@@ -572,12 +570,7 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   cur = align_up(cur + (int64_t)p->fold_inv.size() * 4, 256);
   p->dev_bytes = std::max<int64_t>(cur, 256);
 
-  try {
-    p->staging.assign((size_t)p->dev_bytes, 0);
-  } catch (...) {
-    delete p;
-    return fail(BFMHT_ENOSPACE, "host staging allocation failed");
-  }
+  p->staging.assign((size_t)p->dev_bytes, 0);
   unsigned char *S = p->staging.data();
   auto put = [&](const int64_t *base, int64_t e, double x) {
     if (prec == BFMHT_F64) {
@@ -614,8 +607,30 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
   if (!bj.empty()) std::memcpy(S + p->off_bjobs, bj.data(), bj.size() * sizeof(BwdJob));
   if (!tiles.empty()) std::memcpy(S + p->off_tiles, tiles.data(), tiles.size() * sizeof(Tile));
   if (f->n) std::memcpy(S + p->off_perm, f->perm_x, (size_t)f->n * 4);
-  *out = p;
+  *out = owner.release();
   return BFMHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs, int32_t flags,
+                                  bfmht_plan **out) {
+  if (!out) return fail(BFMHT_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (flags & ~BFMHT_PLAN_FULL_BLOCKS) return fail(BFMHT_EINVAL, "unknown plan flags");
+  if (prec < BFMHT_F64 || prec > BFMHT_BF16X3) return fail(BFMHT_EINVAL, "unknown precision");
+  if (max_nrhs < 1) return fail(BFMHT_EINVAL, "max_nrhs must be >= 1");
+  bfmht_status st = validate(f);
+  if (st != BFMHT_OK) return st;
+  try {
+    return plan_build(f, prec, max_nrhs, (flags & BFMHT_PLAN_FULL_BLOCKS) == 0, out);
+  } catch (const std::bad_alloc &) {
+    return fail(BFMHT_ENOSPACE, "host memory exhausted while building the plan");
+  } catch (...) {
+    return fail(BFMHT_EINVAL, "plan construction failed");
+  }
 }
 
 int64_t bfmht_plan_device_bytes(const bfmht_plan *p) { return p ? p->dev_bytes : -1; }
@@ -806,6 +821,8 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *p, const void *f, int64_t l
 
 // LSQR workspace: the apply workspace, then u, y (n x b), v, z, w (m x b), the
 // norm partial sums and eight scalar arrays, each region 256-byte aligned.
+}  // extern "C"
+
 namespace {
 struct LsqrLayout {
   int64_t apply_ws, u, y, v, z, w, partial, scal, total;
@@ -827,6 +844,8 @@ LsqrLayout lsqr_layout(const bfmht_plan *p, int32_t nrhs) {
   return L;
 }
 }  // namespace
+
+extern "C" {
 
 int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *p, int32_t nrhs) {
   if (!p || nrhs < 0) return -1;
@@ -899,6 +918,8 @@ bfmht_status bfmht_plan_get_tile(const bfmht_plan *p, int32_t transpose, int32_t
 
 // ---- batched ----
 
+}  // extern "C"
+
 namespace {
 struct BatchLayout {
   int64_t total = 0;
@@ -925,17 +946,10 @@ bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const i
   L.total = std::max<int64_t>(cur, 256);
   return BFMHT_OK;
 }
-}  // namespace
 
-int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs) {
-  BatchLayout L;
-  if (batch_layout(plans, count, nrhs, L) != BFMHT_OK) return -1;
-  return L.total;
-}
-
-bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
-                                 const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
-                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
+bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
+                           const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                           int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
   BatchLayout L;
   bfmht_status st = batch_layout(plans, count, nrhs, L);
   if (st != BFMHT_OK) return st;
@@ -1027,6 +1041,29 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
     }
   }
   return BFMHT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs) {
+  try {
+    BatchLayout L;
+    if (batch_layout(plans, count, nrhs, L) != BFMHT_OK) return -1;
+    return L.total;
+  } catch (...) {
+    return -1;
+  }
+}
+
+bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
+                                 const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
+  try {
+    return apply_batched(plans, count, in, ldin, out, ldout, nrhs, transpose, ws, ws_bytes, stream);
+  } catch (...) {
+    return fail(BFMHT_ENOSPACE, "host memory exhausted while grouping the batch");
+  }
 }
 
 }  // extern "C"

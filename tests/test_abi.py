@@ -28,6 +28,37 @@ def test_every_declared_symbol_is_exported():
     assert set(syms) <= set(B.EXPORTED)
 
 
+def _dynamic_c_symbols(path):
+    """Names of the functions an ELF shared library exports with C linkage
+    (defined, global, not C++-mangled), read from its .dynsym table."""
+    import struct
+    data = open(path, "rb").read()
+    assert data[:4] == b"\x7fELF" and data[4] == 2 and data[5] == 1   # 64-bit little-endian
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum = struct.unpack_from("<HH", data, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", data, shoff + i * shentsize) for i in range(shnum)]
+    out = set()
+    for name, typ, flags, addr, off, size, link, info, align, entsize in secs:
+        if typ != 11:   # SHT_DYNSYM
+            continue
+        stroff = secs[link][4]
+        for k in range(size // entsize):
+            st_name, st_info, st_other, st_shndx, st_value, st_size = struct.unpack_from(
+                "<IBBHQQ", data, off + k * entsize)
+            bind, kind = st_info >> 4, st_info & 15
+            if st_shndx == 0 or bind != 1 or kind != 2:   # undefined, not global, not a function
+                continue
+            end = data.index(b"\0", stroff + st_name)
+            sym = data[stroff + st_name:end].decode()
+            if not sym.startswith("_Z"):
+                out.add(sym)
+    return out
+
+
+def test_library_exports_only_declared_c_symbols():
+    assert _dynamic_c_symbols(B.LIB_PATH) == set(declared_symbols())
+
+
 def test_struct_layout_matches_header_order():
     names = [f[0] for f in B.bfmht_factors_host._fields_]
     text = open(HEADER).read()
@@ -97,6 +128,18 @@ def test_rejects_bad_arguments(good):
     _expect(good, B.EINVAL, max_nrhs=0)
     h = ctypes.c_void_p()
     assert B.lib.bfmht_plan_create(None, 0, 1, ctypes.byref(h)) == B.EINVAL
+    assert h.value is None
+    # every failed create leaves *plan NULL, whatever it held before
+    st, keep = B.factors_struct(good)
+    for prec, flags in ((B.F32, 1 << 5), (7, 0)):
+        h = ctypes.c_void_p(0x1234)
+        assert B.lib.bfmht_plan_create_ex(ctypes.byref(st), prec, 1, flags, ctypes.byref(h)) == B.EINVAL
+        assert h.value is None
+    bad = dict(good, perm_x=good["perm_x"].copy())
+    bad["perm_x"][0] = bad["perm_x"][1]
+    st, keep = B.factors_struct(bad)
+    h = ctypes.c_void_p(0x1234)
+    assert B.lib.bfmht_plan_create(ctypes.byref(st), B.F32, 1, ctypes.byref(h)) == B.EINVAL
     assert h.value is None
 
 
