@@ -34,16 +34,13 @@ def lsqr(matvec, rmatvec, b, iters):
         rho = np.hypot(rhobar, beta)
         if rho > 0:
             c, s = rhobar / rho, beta / rho
-        else:
-            c, s = 1.0, 0.0
-        theta = s * alpha
-        rhobar = -c * alpha
-        phi = c * phibar
-        phibar = s * phibar
-        if rho > 0:
+            theta = s * alpha
+            rhobar = -c * alpha
+            phi = c * phibar
+            phibar = s * phibar
             x = x + (phi / rho) * w
             w = v - (theta / rho) * w
-        else:
-            w = v.copy()
+        # else: rhobar = beta = 0, so A^T r = 0 and u = v = 0: the recurrence has
+        # ended, x is a least-squares solution and its residual norm stays phibar
         res.append(abs(phibar))
     return x, np.array(res)

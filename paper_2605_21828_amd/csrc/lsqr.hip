@@ -83,6 +83,9 @@ __global__ __launch_bounds__(kLsqrThreads) void scale_cols_kernel(T *u, int64_t 
 //   rho = sqrt(rhobar^2 + beta^2), c = rhobar / rho, s = beta / rho,
 //   theta = s alpha, rhobar' = -c alpha, phi = c phibar, phibar' = s phibar,
 //   cx = phi / rho (step along w), cw = theta / rho (w update), rnorm = |phibar'|.
+// rho = 0 means rhobar = beta = 0: A^T r = 0 and the bidiagonalization has
+// ended, so the column keeps its iterate (cx = 0, and w = v = 0 from then on)
+// and its residual estimate phibar.
 template <typename T>
 __global__ void rotate_kernel(int b, const T *alpha, const T *beta, T *rhobar, T *phibar, T *cx, T *cw, T *rnorm) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,11 +95,12 @@ __global__ void rotate_kernel(int b, const T *alpha, const T *beta, T *rhobar, T
   const bool live = rho > T(0);
   const T c = live ? rb / rho : T(1), s = live ? be / rho : T(0);
   const T theta = s * al, phi = c * pb;
-  rhobar[j] = -c * al;
-  phibar[j] = s * pb;
+  const T pb1 = live ? s * pb : pb;
+  rhobar[j] = live ? -c * al : rb;
+  phibar[j] = pb1;
   cx[j] = live ? phi / rho : T(0);
   cw[j] = live ? theta / rho : T(0);
-  if (rnorm) rnorm[j] = fabs(s * pb);
+  if (rnorm) rnorm[j] = fabs(pb1);
 }
 
 // x += cx[j] w; w = v - cw[j] w   (x with its own leading dimension)

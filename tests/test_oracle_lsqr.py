@@ -34,3 +34,28 @@ def test_consistent_system_is_solved_exactly():
     xt = rng.standard_normal(10)
     x, res = lsqr(lambda v: A @ v, lambda u: A.T @ u, A @ xt, 40)
     assert np.allclose(x, xt, rtol=1e-10, atol=1e-10) and res[-1] < 1e-9
+
+
+def test_right_hand_side_orthogonal_to_the_range():
+    # A^T b = 0: x = 0 is the least-squares solution and the residual is ||b||
+    # at every step (the recurrence ends at once; the library routine agrees)
+    rng = np.random.default_rng(4)
+    Q = np.linalg.qr(rng.standard_normal((40, 12)))[0]
+    A = Q[:, :8] @ rng.standard_normal((8, 8))
+    b = Q[:, 8:] @ rng.standard_normal(4)
+    assert np.abs(A.T @ b).max() < 1e-12
+    x, res = lsqr(lambda v: A @ v, lambda u: A.T @ u, b, 6)
+    assert np.abs(x).max() < 1e-12
+    assert np.allclose(res, np.linalg.norm(b), rtol=1e-12)
+    ref = spla.lsqr(A, b, atol=0, btol=0, conlim=0, iter_lim=6)
+    assert np.abs(ref[0]).max() < 1e-12 and abs(ref[3] - np.linalg.norm(b)) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("rows,cols", [(6, 0), (0, 5)])
+def test_empty_operator(rows, cols):
+    # no unknowns: the residual is b; no equations: x = 0 and nothing is left
+    b = np.arange(1.0, rows + 1.0)
+    A = np.zeros((rows, cols))
+    x, res = lsqr(lambda v: A @ v, lambda u: A.T @ u, b, 3)
+    assert x.shape == (cols,) and not np.any(x)
+    assert np.allclose(res, np.linalg.norm(b), rtol=1e-15)
