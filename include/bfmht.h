@@ -20,7 +20,9 @@
  *    level 0 computes y_0j = P_0j c[koff[j] : koff[j+1]], and the last stage
  *    writes f[perm_x[xoff[i] + t]] = (U_i y_Li)[t].
  *  - Dense right-hand-side blocks are row-major: row r, column (RHS) s at
- *    ptr[r * ld + s], ld >= nrhs.  Rows are points (f) or modes (c).
+ *    ptr[r * ld + s], ld >= nrhs.  Rows are points (f) or modes (c).  A block
+ *    with no rows (n = 0 or m = 0) is never read or written: it may be NULL
+ *    and its ld is not checked.
  *  - All device pointers are caller-owned (PyTorch allocates them).  The plan
  *    owns host metadata only and refers to device memory inside the buffer
  *    given to bfmht_plan_upload.
@@ -160,14 +162,15 @@ bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_
  * truncated Karhunen-Loeve expansion, eq. KL-expansion, y = Phi S^(1/2) z is this call with
  * s = S^(1/2) and c = z).  s: device, m elements, same element type as c.
  * Otherwise as bfmht_apply; diag(s) c is formed in the workspace, c is left
- * unchanged.  EINVAL if s is NULL. */
+ * unchanged.  EINVAL if s is NULL (and m > 0). */
 bfmht_status bfmht_apply_scaled(const bfmht_plan *plan, const void *s, const void *c, int64_t ldc, void *f,
                                 int64_t ldf, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream);
 
 /* Scaled analysis g = diag(s) Phi~^T f.  With s the spectral density S on the
  * eigenvalues, bfmht_apply(bfmht_apply_transpose_scaled(f)) is the covariance
  * matrix-vector product Phi S Phi^T f of the truncated kernel expansion
- * (Sec. 7.2, eq. kernel-representation).  Otherwise as bfmht_apply_transpose.  EINVAL if s is NULL. */
+ * (Sec. 7.2, eq. kernel-representation).  Otherwise as bfmht_apply_transpose.  EINVAL if s is NULL
+ * (and m > 0). */
 bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *plan, const void *s, const void *f, int64_t ldf,
                                           void *g, int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes,
                                           void *stream);
@@ -184,7 +187,8 @@ bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *plan, const void *s,
  * bfmht_lsqr_workspace_bytes(plan, nrhs) bytes, 256-byte aligned, not
  * overlapping f, x or rnorm.  EINVAL on bad arguments or iters < 0, ESTATE if
  * not uploaded, ENOSPACE if ws is too small.  A column whose residual or
- * projected residual vanishes keeps its iterate from then on. */
+ * projected residual vanishes keeps its iterate and its residual estimate
+ * from then on (the estimate stays ||f|| when Phi~^T f = 0). */
 bfmht_status bfmht_lsqr(const bfmht_plan *plan, const void *f, int64_t ldf, void *x, int64_t ldx, int32_t nrhs,
                         int32_t iters, void *rnorm, void *ws, int64_t ws_bytes, void *stream);
 int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);

@@ -668,14 +668,17 @@ void bfmht_plan_destroy(bfmht_plan *p) { delete p; }
 
 namespace {
 
-bfmht_status check_call(const bfmht_plan *p, const void *in, int64_t ldin, const void *out, int64_t ldout,
-                        int32_t nrhs, const void *ws, int64_t ws_bytes) {
+// in has rows_in rows and out rows_out rows; a block with no rows may be NULL.
+bfmht_status check_call(const bfmht_plan *p, const void *in, int64_t rows_in, int64_t ldin, const void *out,
+                        int64_t rows_out, int64_t ldout, int32_t nrhs, const void *ws, int64_t ws_bytes) {
   if (!p) return fail(BFMHT_EINVAL, "plan is NULL");
   if (!p->uploaded) return fail(BFMHT_ESTATE, "plan not uploaded");
   if (nrhs < 0) return fail(BFMHT_EINVAL, "nrhs < 0");
   if (nrhs == 0) return BFMHT_OK;
-  if (!in || !out || !ws) return fail(BFMHT_EINVAL, "NULL input, output or workspace");
-  if (ldin < nrhs || ldout < nrhs) return fail(BFMHT_EINVAL, "ld smaller than nrhs");
+  if ((!in && rows_in > 0) || (!out && rows_out > 0) || !ws)
+    return fail(BFMHT_EINVAL, "NULL input, output or workspace");
+  if ((rows_in > 0 && ldin < nrhs) || (rows_out > 0 && ldout < nrhs))
+    return fail(BFMHT_EINVAL, "ld smaller than nrhs");
   if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
   if (ws_bytes < bfmht_workspace_bytes(p, nrhs)) return fail(BFMHT_ENOSPACE, "workspace too small");
   return BFMHT_OK;
@@ -747,7 +750,7 @@ int gather_input(const bfmht_plan *p, const void *in, int64_t ldin, int32_t nrhs
 
 bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out, int64_t ldout,
                        int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
-  bfmht_status st = check_call(p, in, ldin, out, ldout, nrhs, ws, ws_bytes);
+  bfmht_status st = check_call(p, in, fwd ? p->m : p->n, ldin, out, fwd ? p->n : p->m, ldout, nrhs, ws, ws_bytes);
   if (st != BFMHT_OK || nrhs == 0) return st;
   char *const buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + level_buffer_bytes(p, nrhs)};
   if (!fwd) {
@@ -793,9 +796,9 @@ bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *
 
 bfmht_status bfmht_apply_scaled(const bfmht_plan *p, const void *s, const void *c, int64_t ldc, void *f, int64_t ldf,
                                 int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
-  bfmht_status st = check_call(p, c, ldc, f, ldf, nrhs, ws, ws_bytes);
+  bfmht_status st = check_call(p, c, p->m, ldc, f, p->n, ldf, nrhs, ws, ws_bytes);
   if (st != BFMHT_OK || nrhs == 0) return st;
-  if (!s) return fail(BFMHT_EINVAL, "scale vector is NULL");
+  if (!s && p->m > 0) return fail(BFMHT_EINVAL, "scale vector is NULL");
   // diag(s) c goes to the second level buffer, which stage 0 does not write and
   // stage 1 overwrites only after stage 0 has read it
   char *scaled = static_cast<char *>(ws) + level_buffer_bytes(p, nrhs);
@@ -806,7 +809,7 @@ bfmht_status bfmht_apply_scaled(const bfmht_plan *p, const void *s, const void *
 
 bfmht_status bfmht_apply_transpose_scaled(const bfmht_plan *p, const void *s, const void *f, int64_t ldf, void *g,
                                           int64_t ldg, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
-  if (nrhs > 0 && !s) return fail(BFMHT_EINVAL, "scale vector is NULL");
+  if (p && nrhs > 0 && !s && p->m > 0) return fail(BFMHT_EINVAL, "scale vector is NULL");
   bfmht_status st = run_apply(p, false, f, ldf, g, ldg, nrhs, ws, ws_bytes, stream);
   if (st != BFMHT_OK || nrhs == 0) return st;
   const int e = launch_scale_rows((int)p->esz, s, g, ldg, p->m, g, ldg, nrhs, stream);
@@ -858,8 +861,9 @@ bfmht_status bfmht_lsqr(const bfmht_plan *p, const void *f, int64_t ldf, void *x
   if (!p->uploaded) return fail(BFMHT_ESTATE, "plan not uploaded");
   if (nrhs < 0 || iters < 0) return fail(BFMHT_EINVAL, "nrhs or iters < 0");
   if (nrhs == 0) return BFMHT_OK;
-  if (!f || !x || !ws) return fail(BFMHT_EINVAL, "NULL right-hand side, solution or workspace");
-  if (ldf < nrhs || ldx < nrhs) return fail(BFMHT_EINVAL, "ld smaller than nrhs");
+  if ((!f && p->n > 0) || (!x && p->m > 0) || !ws)
+    return fail(BFMHT_EINVAL, "NULL right-hand side, solution or workspace");
+  if ((p->n > 0 && ldf < nrhs) || (p->m > 0 && ldx < nrhs)) return fail(BFMHT_EINVAL, "ld smaller than nrhs");
   if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
   const LsqrLayout L = lsqr_layout(p, nrhs);
   if (ws_bytes < L.total) return fail(BFMHT_ENOSPACE, "workspace too small for LSQR");
@@ -964,8 +968,10 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
     const bfmht_plan *p = plans[i];
     if (nrhs[i] == 0) continue;
     if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
-    if (!in[i] || !out[i]) return fail(BFMHT_EINVAL, "NULL input or output in batch");
-    if (ldin[i] < nrhs[i] || ldout[i] < nrhs[i]) return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
+    if ((!in[i] && (fwd ? p->m : p->n) > 0) || (!out[i] && (fwd ? p->n : p->m) > 0))
+      return fail(BFMHT_EINVAL, "NULL input or output in batch");
+    if (((fwd ? p->m : p->n) > 0 && ldin[i] < nrhs[i]) || ((fwd ? p->n : p->m) > 0 && ldout[i] < nrhs[i]))
+      return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
     char *base = static_cast<char *>(ws) + L.buf_off[i];
     char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
     if (!fwd) {
