@@ -664,7 +664,7 @@ def main():
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched32":
         return bench_batched(args)
