@@ -263,3 +263,25 @@ def test_fourier_factor_set_is_applied_in_compact_form():
             if 0 < r < k:
                 expect += r * r
     assert save == expect
+
+
+def test_tile_shapes_are_host_state(good):
+    # stage count L + 2, default 64 x 0 (smallest width covering nrhs), the six
+    # legal shapes accepted per direction and stage, anything else rejected
+    h = B.bfmht_plan_create(good, B.F32, 4)
+    try:
+        S = B.bfmht_plan_num_stages(h)
+        assert S == int(good["L"]) + 2
+        assert all(B.bfmht_plan_get_tile(h, d, k) == (64, 0) for d in (0, 1) for k in range(S))
+        for k in range(S):
+            B.bfmht_plan_set_tile(h, 1, k, (64, 128)[k % 2], (0, 16, 32, 64)[k % 4])
+        assert [B.bfmht_plan_get_tile(h, 1, k) for k in range(S)] == \
+            [((64, 128)[k % 2], (0, 16, 32, 64)[k % 4]) for k in range(S)]
+        assert all(B.bfmht_plan_get_tile(h, 0, k) == (64, 0) for k in range(S))   # directions are separate
+        for bad in ((1, S, 64, 16), (1, -1, 64, 16), (0, 0, 96, 16), (0, 0, 64, 48), (0, 0, 0, 16)):
+            with pytest.raises(B.BfmhtError) as e:
+                B.bfmht_plan_set_tile(h, *bad)
+            assert e.value.status == B.EINVAL
+    finally:
+        B.bfmht_plan_destroy(h)
+    assert B.lib.bfmht_plan_num_stages(None) == -1
