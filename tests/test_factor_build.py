@@ -70,3 +70,14 @@ def test_factor_set_is_unchanged_by_the_shortcut(monkeypatch):
     for key in ("rank", "ident", "P", "P_off", "U", "U_off", "skel_L", "perm_x", "xoff", "koff"):
         assert np.array_equal(fs1[key], fs2[key]), key
     assert fs1["ident"].sum() > 0
+
+
+def test_parallel_build_equals_serial_build():
+    # blocks of a level are independent; the process pool returns them out of
+    # order and the builder must place each by its id
+    rng = np.random.default_rng(6)
+    pts = rng.uniform(-np.pi, np.pi, (2048, 2))
+    fs1, _ = fio.fourier_factors(pts, 256, 32, 1e-8, workers=1, cache=False)
+    fs2, _ = fio.fourier_factors(pts, 256, 32, 1e-8, workers=3, cache=False)
+    for key in ("rank", "ident", "P", "P_off", "U", "U_off", "skel_L"):
+        assert np.array_equal(fs1[key], fs2[key]), key
