@@ -544,6 +544,9 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
     p->cols[d].assign(p->stages.size(), 0);
   }
 
+  // job fields and kernels index the row-index table with 32-bit offsets
+  if (p->maps.size() >= (size_t)(1ll << 31)) return fail(BFMHT_EINVAL, "row-index table exceeds 2^31 entries");
+
   // Device layout.  Every pool region ends in a zero tail of at least one
   // reduction chunk (128 bytes for every element type): the kernels read whole
   // chunks past a row's end without a guard.
