@@ -1,0 +1,61 @@
+"""Parity at the full size of the perturbed-sphere workload (GPU, through the C ABI).
+
+40962 vertices of a perturbed level-6 icosphere, the 4096 lowest
+Laplace-Beltrami eigenvectors (cotangent stiffness, lumped mass), Fiedler-tree
+leaves of 64, tol 1e-8, 256 right-hand sides: the configuration the benchmark
+times, with the tile shapes its autotuner picks.  The dense eigenvector matrix
+fits in host memory, so every output is checked against the dense FP64
+transform of the same Phi (per-column relative 2-norm, max over columns); the
+FP64 apply is also checked against the oracle's butterfly apply of the same
+factors.
+"""
+import numpy as np
+import pytest
+
+from oracle import butterfly as ob
+from oracle import dense as od
+from paper_2605_21828_amd import workloads as wl
+from paper_2605_21828_amd.factor import io as fio
+
+pytestmark = pytest.mark.gpu
+
+# dense FP64 bound: the ID tolerance compounds over the levels (measured
+# 1.2e-8 for FP64); the FP32 and three-term split bound is the target 1e-5,
+# the two-term split carries its representation error (about 3e-5)
+TOL = {"f64": 1e-7, "f32": 1e-5, "bf16x3": 1e-5, "bf16x2": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def sphere(gpu):
+    s = wl.SPHERE
+    print("building the level-%d sphere problem, m = %d" % (s["level"], s["m"]), flush=True)
+    fs, prob = fio.sphere_factors(s["level"], s["wid"], s["m"], s["leaf"], s["tol"], cache=True)
+    Phi = prob["Phi"]
+    c = wl.coefficients(s["wid"], s["m"], s["nrhs"])
+    fv = wl.values(s["wid"], Phi.shape[0], s["nrhs"])
+    return fs, Phi, c, fv, Phi @ c, Phi.T @ fv
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f32", "bf16x2", "f64"])
+def test_sphere_full_size_vs_dense(sphere, prec):
+    import torch
+    from paper_2605_21828_amd.autotune import tune_plan
+    from paper_2605_21828_amd.bfmht import Plan
+    fs, Phi, c, fv, ref_f, ref_g = sphere
+    b = c.shape[1]
+    p = Plan(fs, prec, max_nrhs=b)
+    tune_plan(p, fs, b, reps=3, use_cache=False)
+    print("sphere40962", prec, "tuned", flush=True)
+    dt = p.dtype
+    f = p.apply(torch.tensor(c, dtype=dt, device="cuda"))
+    g = p.apply_t(torch.tensor(fv, dtype=dt, device="cuda"))
+    torch.cuda.synchronize()
+    f, g = f.double().cpu().numpy(), g.double().cpu().numpy()
+    ef, eg = od.rel_err_cols(f, ref_f)[0], od.rel_err_cols(g, ref_g)[0]
+    print("sphere40962 %s synthesis %.3g analysis %.3g" % (prec, ef, eg), flush=True)
+    assert ef <= TOL[prec] and eg <= TOL[prec]
+    if prec == "f64":   # same factors, FP64 throughout: the oracle's butterfly apply
+        cols = slice(0, 8)
+        of, og = ob.apply(fs, c[:, cols]), ob.apply_transpose(fs, fv[:, cols])
+        assert np.linalg.norm(f[:, cols] - of) <= 1e-12 * np.linalg.norm(of)
+        assert np.linalg.norm(g[:, cols] - og) <= 1e-12 * np.linalg.norm(og)
