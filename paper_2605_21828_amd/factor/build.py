@@ -110,27 +110,38 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
             U_list.append(np.ascontiguousarray(blocks(rows, cols)))
         else:
             U_list.append(np.zeros((rows.size, cols.size)))
+    # Pack the blocks into one array each, releasing every block once it is
+    # copied, so the peak host memory stays near one copy of the factors.
     P_off = np.full((L + 1, nb), -1, dtype=np.int64)
-    chunks, off = [], 0
+    off = 0
     for lvl in range(L + 1):
         for q in range(nb):
             P = P_blocks[lvl][q]
             if P is not None and not ident[lvl, q]:
                 P_off[lvl, q] = off
-                chunks.append(np.ascontiguousarray(P, dtype=np.float64).ravel())
                 off += P.size
+    P_all = np.empty(off, dtype=np.float64)
+    for lvl in range(L + 1):
+        for q in range(nb):
+            if P_off[lvl, q] >= 0:
+                P = P_blocks[lvl][q]
+                P_all[P_off[lvl, q]:P_off[lvl, q] + P.size] = np.asarray(P, dtype=np.float64).ravel()
+            P_blocks[lvl][q] = None
     U_off = np.zeros(nb, dtype=np.int64)
-    uchunks, uo = [], 0
+    uo = 0
     for i in range(nb):
         U_off[i] = uo
-        uchunks.append(U_list[i].ravel())
         uo += U_list[i].size
+    U_all = np.empty(uo, dtype=np.float64)
+    for i in range(nb):
+        U_all[U_off[i]:U_off[i] + U_list[i].size] = U_list[i].ravel()
+        U_list[i] = None
     return dict(
         n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol),
         perm_x=perm_x, xoff=xoff, koff=koff, rank=rank, ident=ident,
-        P=np.concatenate(chunks) if chunks else np.zeros(0),
+        P=P_all,
         P_off=P_off,
-        U=np.concatenate(uchunks) if uchunks else np.zeros(0),
+        U=U_all,
         U_off=U_off,
         skel_L=np.concatenate([J_prev[i] for i in range(nb)]).astype(np.int64),
         build_stats=np.array([[s["level"], s["seconds"], s["rank_min"], s["rank_max"],
