@@ -16,7 +16,10 @@ Modules
   sparse     the same factor set multiplied out as a product of block-sparse
              matrices (Sec. 2, Remark on the sparse-factor view); an independent
              formulation used to pin O2 at tiny sizes
-  sphere_check  spherical-harmonic eigenvalue check of a discrete Laplacian
+  lsqr       LSQR (Paige and Saunders), the least-squares solver the inverse
+             transform uses (Sec. 7.1, eq. inverse-MHT)
+  fem        element-by-element linear finite-element stiffness and lumped mass
+             on a triangle mesh, a second formulation of the cotangent Laplacian
 
 Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py).
 """

@@ -18,11 +18,6 @@ Everything is brute force and float64.
 import numpy as np
 
 
-def mode_count_in_box(K):
-    """Number of real modes with 0 <= k1, k2 <= K (one per lattice point of [-K, K]^2)."""
-    return (2 * K + 1) ** 2
-
-
 def fourier_modes(m):
     """The first m real modes, as an int64 array of rows (k1, k2, s1, s2).
 
