@@ -115,7 +115,9 @@ int launch_gemv_stage(int prec, bool fwd, const StageArgs &a, void *stream);
 int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *stream);
 
 // dst[r] = sum over the C copies k of src[inv[r C + k]] (rows of nrhs elements of
-// esz bytes), as a balanced pairwise tree in copy order; C a power of two.
+// esz bytes), as a balanced pairwise tree in copy order; C a power of two, at
+// most kFoldMaxCopies.
+constexpr int64_t kFoldMaxCopies = 1 << 15;
 int launch_fold_sum(int esz, const void *src, int64_t lds, const int32_t *inv, int C, int64_t rows, void *dst,
                     int64_t ldd, int nrhs, void *stream);
 // dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).

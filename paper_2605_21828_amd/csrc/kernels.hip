@@ -1193,7 +1193,7 @@ int launch_fold_sum(int esz, const void *src, int64_t lds, const int32_t *inv, i
                     int64_t ldd, int nrhs, void *stream) {
   const int64_t total = rows * nrhs;
   if (total == 0) return 0;
-  if (C < 1 || C > (1 << 15) || (C & (C - 1))) return (int)hipErrorInvalidValue;
+  if (C < 1 || C > kFoldMaxCopies || (C & (C - 1))) return (int)hipErrorInvalidValue;
   const unsigned grid = (unsigned)std::min<int64_t>((total + kNT - 1) / kNT, 8192);
   if (esz == 8)
     hipLaunchKernelGGL((fold_sum_kernel<double>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,

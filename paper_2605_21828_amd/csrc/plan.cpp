@@ -75,7 +75,8 @@ struct bfmht_plan {
   int64_t stored_fwd = 0;          // factor entries of the forward pool (compact blocks store T only)
   std::vector<int32_t> maps;       // forward jobs' row-index table
   int64_t off_maps = 0;
-  int nfold = 0;                   // leading all-identity levels (folded, see plan creation)
+  int nfold = 0;                   // transposed direction: folded all-identity levels (0: every stage runs)
+  int fwd_edge = 0;                // forward direction: the first stage that runs (leading all-identity levels skipped)
   int64_t fold_copies = 0;         // copies of each row of c at level nfold-1
   std::vector<int32_t> fold_inv;   // per row of c, its level nfold-1 rows in space-node order
   int64_t off_fold = 0;
@@ -497,11 +498,14 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       pi.swap(nx);
     }
     for (int k = 0; k < nfold; ++k) p->stages[k].skip = true;
+    p->fwd_edge = nfold;
     // Transposed direction: the folded levels sum the copies of each row of c,
     // pairwise over the space nodes (a balanced tree).  One gather-sum over the
-    // level nfold-1 rows replaces those stages in a single apply.
+    // level nfold-1 rows replaces those stages in a single apply.  The gather-sum
+    // kernel takes at most 2^15 copies; deeper runs of identity levels keep their
+    // transposed stages (then nfold stays 0).
     const int64_t C = 1ll << (nfold - 1), rows = off[nfold - 1][nb];
-    if (rows == f->m * C) {
+    if (C <= kFoldMaxCopies && rows == f->m * C) {
       std::vector<int32_t> cnt((size_t)f->m, 0);
       p->fold_inv.assign((size_t)rows, -1);
       bool ok = true;
@@ -802,9 +806,11 @@ bfmht_status bfmht_apply_scaled(const bfmht_plan *p, const void *s, const void *
   bfmht_status st = check_call(p, c, p->m, ldc, f, p->n, ldf, nrhs, ws, ws_bytes);
   if (st != BFMHT_OK || nrhs == 0) return st;
   if (!s && p->m > 0) return fail(BFMHT_EINVAL, "scale vector is NULL");
-  // diag(s) c goes to the second level buffer, which stage 0 does not write and
-  // stage 1 overwrites only after stage 0 has read it
-  char *scaled = static_cast<char *>(ws) + level_buffer_bytes(p, nrhs);
+  // diag(s) c goes to the level buffer that the first forward stage to run
+  // (level fwd_edge, after the folded identity levels) does not write; the next
+  // stage overwrites it only after that stage has read it.  A first stage that
+  // is the leaf stage writes f and neither buffer.
+  char *scaled = static_cast<char *>(ws) + ((p->fwd_edge & 1) ^ 1) * level_buffer_bytes(p, nrhs);
   const int e = launch_scale_rows((int)p->esz, s, c, ldc, p->m, scaled, nrhs, nrhs, stream);
   if (e) return fail(BFMHT_EHIP, std::string("scale launch: ") + hipGetErrorString((hipError_t)e));
   return run_apply(p, true, scaled, nrhs, f, ldf, nrhs, ws, ws_bytes, stream);
@@ -889,6 +895,10 @@ bfmht_status bfmht_lsqr(const bfmht_plan *p, const void *f, int64_t ldf, void *x
   if ((st = ok((int)hipMemcpyAsync(rhobar, alpha, b * e, hipMemcpyDeviceToDevice, (hipStream_t)stream), "LSQR start")))
     return st;
   if ((st = ok(lsqr_init(es, x, ldx, w, v, p->m, nrhs, stream), "LSQR start"))) return st;
+  // with no step taken the residual estimate is beta_1 = ||f|| (x = 0)
+  if (iters == 0 && rnorm &&
+      (st = ok((int)hipMemcpyAsync(rnorm, phibar, b * e, hipMemcpyDeviceToDevice, (hipStream_t)stream), "LSQR start")))
+    return st;
   for (int32_t it = 0; it < iters; ++it) {
     // beta_{i+1} u_{i+1} = Phi~ v_i - alpha_i u_i
     if ((st = run_apply(p, true, v, b, y, b, nrhs, aws, aws_bytes, stream))) return st;

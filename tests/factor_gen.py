@@ -19,11 +19,12 @@ def _partition(rng, total, parts, allow_empty=True):
 
 
 def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=True, identity_values=False,
-                      p_id_form=0.0):
+                      p_id_form=0.0, ident_levels=0):
     """Random factor set.  identity_values=True makes every P the identity and
     every U_i a 0/1 selection so that the apply is an exact permutation.
     p_id_form: probability that a non-identity block with 0 < rank < inputs has
-    the column-ID form P = [I T] Pi^T (r random columns hold e_1 .. e_r)."""
+    the column-ID form P = [I T] Pi^T (r random columns hold e_1 .. e_r).
+    ident_levels: levels 0 .. ident_levels-1 hold identity blocks only."""
     rng = np.random.default_rng(seed)
     nb = 1 << L
     perm = rng.permutation(n).astype(np.int32)
@@ -42,7 +43,7 @@ def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=Tr
                 i, j = divmod(q, nf)
                 q1 = (i >> 1) * 2 * nf + 2 * j
                 rin = int(rank[lvl - 1, q1] + rank[lvl - 1, q1 + 1])
-            if identity_values or rng.random() < p_ident and (max_rank is None or rin <= max_rank):
+            if identity_values or lvl < ident_levels or (rng.random() < p_ident and (max_rank is None or rin <= max_rank)):
                 rank[lvl, q] = rin
                 ident[lvl, q] = 1
                 continue
