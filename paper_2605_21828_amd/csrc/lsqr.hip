@@ -6,7 +6,8 @@
 //
 // Every vector is row-major (rows x b, ld = b unless stated) and every scalar
 // is an array of b, one per right-hand side.  Column norms are deterministic:
-// per-block partial sums in a fixed order, then one thread per column.
+// per-block partial sums in a fixed order, then one workgroup per column
+// reduces its column's partial sums with a fixed tree.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

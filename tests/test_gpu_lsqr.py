@@ -107,3 +107,15 @@ def test_lsqr_argument_errors(gpu, grid):
     assert e.value.status == B.ENOSPACE
     B.bfmht_lsqr(p.handle, ft.data_ptr(), 1, x.data_ptr(), 1, 1, 0, None, wp, need, 0)
     assert not _np(x).any()       # zero steps leave the zero iterate
+
+
+def test_lsqr_zero_steps_reports_the_norm_of_f(gpu, grid):
+    """With no step the iterate is zero and the residual estimate is ||f|| per column."""
+    import torch
+    from paper_2605_21828_amd.bfmht import Plan
+    w, fs, md, c_star, f = grid
+    for prec, dt, tol in (("f64", torch.float64, 1e-13), ("f32", torch.float32, 1e-6)):
+        p = Plan(fs, prec, max_nrhs=3)
+        x, rn = p.lsqr(_t(f, dt), 0)
+        assert not _np(x).any()
+        assert np.allclose(_np(rn), np.linalg.norm(f, axis=0), rtol=tol, atol=0)
