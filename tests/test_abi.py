@@ -285,3 +285,18 @@ def test_tile_shapes_are_host_state(good):
     finally:
         B.bfmht_plan_destroy(h)
     assert B.lib.bfmht_plan_num_stages(None) == -1
+
+
+def test_deep_all_identity_factor_set_creates_a_plan():
+    """17 levels of identity blocks (more row copies than the transposed
+    gather-sum takes): the plan keeps those transposed stages instead of folding
+    them, and creation, sizes and stage counts are unaffected."""
+    fs = random_factor_set(80, 1 << 16, 1, 16, ident_levels=17, allow_empty=True)
+    assert fs["ident"].all()
+    h = B.bfmht_plan_create(fs, B.F32, 1)
+    try:
+        assert B.bfmht_plan_num_stages(h) == 18
+        assert B.bfmht_plan_stored_entries(h, False) == fs["U"].size
+        assert B.bfmht_workspace_bytes(h, 1) >= 2 * (1 << 16) * 4
+    finally:
+        B.bfmht_plan_destroy(h)

@@ -213,3 +213,26 @@ def test_folded_identity_levels_match_unfolded_bitwise(gpu, nrhs):
         tol = 1e-12 if prec == "f64" else 1e-5
         assert od.rel_err_cols(g_single, ob.apply_transpose(fs, f.double().cpu().numpy()))[0] <= tol
         assert od.rel_err_cols(y_single, ob.apply(fs, c.double().cpu().numpy()))[0] <= tol
+
+
+@pytest.fixture(scope="module")
+def deep_identity():
+    """Depth 16, one point per space leaf, a single mode: every level is all
+    identities, so folding them would need 2^16 copies per row of c (beyond the
+    gather-sum's 2^15); the transposed apply then runs those stages one by one."""
+    fs = random_factor_set(80, 1 << 16, 1, 16, ident_levels=17, allow_empty=True)
+    assert fs["ident"].all()
+    rng = np.random.default_rng(81)
+    c = rng.standard_normal((1, 16))
+    f = rng.standard_normal((1 << 16, 16))
+    return fs, c, f, ob.apply(fs, c), ob.apply_transpose(fs, f)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_deep_identity_levels_beyond_fold_limit(gpu, deep_identity, prec, tol):
+    from paper_2605_21828_amd.bfmht import Plan
+    fs, c, f, y_ref, g_ref = deep_identity
+    for b in (1, 16):
+        p = Plan(fs, prec, max_nrhs=b)
+        assert od.rel_err_cols(_np(p.apply(_t(c[:, :b], _dt(prec)))), y_ref[:, :b])[0] <= tol
+        assert od.rel_err_cols(_np(p.apply_t(_t(f[:, :b], _dt(prec)))), g_ref[:, :b])[0] <= tol
