@@ -292,11 +292,31 @@ class Plan:
             x = x.contiguous()
         return x, squeeze
 
+    def _out(self, out, rows, b):
+        """The output block: a new (rows, b) tensor, or `out` after checking that
+        the library may write rows x b elements into it (its device, element
+        type, shape, unit column stride and row stride >= b); a 1-D out of
+        `rows` elements is accepted for b = 1."""
+        torch = self.torch
+        if out is None:
+            return torch.empty((rows, b), dtype=self.dtype, device=self.device)
+        if out.device != self.device or out.dtype != self.dtype:
+            raise ValueError("out must be a %s tensor on %s, got %s on %s"
+                             % (self.dtype, self.device, out.dtype, out.device))
+        if out.dim() == 1 and b == 1:
+            out = out.unsqueeze(1)
+        if out.dim() != 2 or tuple(out.shape) != (rows, b):
+            raise ValueError("out must have shape (%d, %d), got %s" % (rows, b, tuple(out.shape)))
+        if rows > 0 and b > 0 and ((b > 1 and out.stride(1) != 1) or out.stride(0) < b):
+            raise ValueError("out must have unit column stride and row stride >= %d, got strides %s"
+                             % (b, tuple(out.stride())))
+        return out
+
     def apply(self, c, out=None):
         torch = self.torch
         c, squeeze = self._prep(c, self.m)
         b = c.shape[1]
-        f = out if out is not None else torch.empty((self.n, b), dtype=self.dtype, device=self.device)
+        f = self._out(out, self.n, b)
         ws, wsb = self.workspace(b)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         bfmht_apply(self.handle, c.data_ptr(), c.stride(0), f.data_ptr(), f.stride(0), b, ws, wsb, stream)
@@ -306,7 +326,7 @@ class Plan:
         torch = self.torch
         f, squeeze = self._prep(f, self.n)
         b = f.shape[1]
-        g = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        g = self._out(out, self.m, b)
         ws, wsb = self.workspace(b)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         bfmht_apply_transpose(self.handle, f.data_ptr(), f.stride(0), g.data_ptr(), g.stride(0), b, ws, wsb, stream)
@@ -323,7 +343,7 @@ class Plan:
         s = self._scale(s)
         c, squeeze = self._prep(c, self.m)
         b = c.shape[1]
-        f = out if out is not None else torch.empty((self.n, b), dtype=self.dtype, device=self.device)
+        f = self._out(out, self.n, b)
         ws, wsb = self.workspace(b)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         bfmht_apply_scaled(self.handle, s.data_ptr(), c.data_ptr(), c.stride(0), f.data_ptr(), f.stride(0), b, ws,
@@ -336,7 +356,7 @@ class Plan:
         s = self._scale(s)
         f, squeeze = self._prep(f, self.n)
         b = f.shape[1]
-        g = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        g = self._out(out, self.m, b)
         ws, wsb = self.workspace(b)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         bfmht_apply_transpose_scaled(self.handle, s.data_ptr(), f.data_ptr(), f.stride(0), g.data_ptr(),
@@ -349,7 +369,7 @@ class Plan:
         torch = self.torch
         f, squeeze = self._prep(f, self.n)
         b = f.shape[1]
-        x = out if out is not None else torch.empty((self.m, b), dtype=self.dtype, device=self.device)
+        x = self._out(out, self.m, b)
         rnorm = torch.empty(b, dtype=self.dtype, device=self.device)
         need = bfmht_lsqr_workspace_bytes(self.handle, b)
         ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
@@ -401,10 +421,15 @@ class Batch:
 
     def launch(self, inputs, outputs, transpose=False):
         torch = self.torch
-        xs = []
-        for p, x in zip(self.plans, inputs):
+        if len(inputs) != len(self.plans) or len(outputs) != len(self.plans):
+            raise ValueError("a batch of %d plans needs %d inputs and %d outputs, got %d and %d"
+                             % (len(self.plans), len(self.plans), len(self.plans), len(inputs), len(outputs)))
+        xs, ys = [], []
+        for p, x, y in zip(self.plans, inputs, outputs):
             x, _ = p._prep(x, p.n if transpose else p.m)
             xs.append(x)
+            ys.append(p._out(y, p.m if transpose else p.n, int(x.shape[1])))
+        outputs = ys
         nrhs = [int(x.shape[1]) for x in xs]
         ws, wsb = self.workspace(nrhs)
         stream = torch.cuda.current_stream(self.device).cuda_stream

@@ -269,3 +269,39 @@ def test_sphere_vs_dense(gpu, small_sphere, prec, tol):
     dt = torch.float64 if prec == "f64" else torch.float32
     assert _rel(_np(p.apply(_t(c, dt))), Phi @ c) <= tol
     assert _rel(_np(p.apply_t(_t(f, dt))), Phi.T @ f) <= tol
+
+
+def test_binding_rejects_bad_out_tensors(gpu):
+    """out= tensors are checked before the library writes into them."""
+    import torch
+    from factor_gen import random_factor_set
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    fs = random_factor_set(31, 300, 200, 4, max_rank=40)
+    p = Plan(fs, "f32", max_nrhs=4)
+    c = torch.zeros((200, 4), dtype=torch.float32, device="cuda")
+    f = torch.zeros((300, 4), dtype=torch.float32, device="cuda")
+    bad = [torch.empty((299, 4), dtype=torch.float32, device="cuda"),      # too few rows
+           torch.empty((300, 3), dtype=torch.float32, device="cuda"),      # too few columns
+           torch.empty((300, 4), dtype=torch.float64, device="cuda"),      # wrong element type
+           torch.empty((300, 4), dtype=torch.float32),                     # host memory
+           torch.empty((4, 300), dtype=torch.float32, device="cuda").t()]  # column stride 300
+    for out in bad:
+        with pytest.raises(ValueError):
+            p.apply(c, out=out)
+    with pytest.raises(ValueError):
+        p.apply_t(f, out=torch.empty((201, 4), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        p.apply_scaled(torch.ones(200, device="cuda"), c, out=bad[0])
+    with pytest.raises(ValueError):
+        p.apply_t_scaled(torch.ones(200, device="cuda"), f, out=bad[2])
+    with pytest.raises(ValueError):
+        Batch([p, p]).launch([c], [f])                                     # fewer inputs than plans
+    with pytest.raises(ValueError):
+        Batch([p]).launch([c], [bad[1]])
+    # a 1-D out takes a single column; a wider row stride is fine
+    y1 = torch.empty(300, dtype=torch.float32, device="cuda")
+    p.apply(c[:, 0], out=y1)
+    wide = torch.zeros((300, 6), dtype=torch.float32, device="cuda")
+    p.apply(c, out=wide[:, 1:5])
+    torch.cuda.synchronize()
+    assert torch.equal(wide[:, 1:5], p.apply(c))
