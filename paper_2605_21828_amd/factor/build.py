@@ -11,7 +11,9 @@ Sec. 4 possible).  Blocks of one level are independent and run in a process
 pool; skeletons of the previous level are the only state passed on.
 
 `blocks(rows, cols)` must return Phi[rows][:, cols] in float64; rows=None means
-all points.
+all points.  A blocks object that also has `tree_ordered(perm_x)` hands back a
+callable `(a, b, cols) -> Phi[perm_x[a:b]][:, cols]`, used instead, which can
+read the rows of a space node as one contiguous range.
 """
 import os
 import time
@@ -25,11 +27,13 @@ _CTX = {}
 
 def _id_task(task):
     lvl, q, a, b, cols = task
-    blocks, perm, tol = _CTX["blocks"], _CTX["perm"], _CTX["tol"]
-    rows = None if lvl == 0 else perm[a:b]
+    blocks, perm, tol, tree = _CTX["blocks"], _CTX["perm"], _CTX["tol"], _CTX["tree"]
     if cols.size == 0:
         return lvl, q, cols, None, True
-    A = blocks(rows, cols)
+    if tree is not None:
+        A = tree(a, b, cols)
+    else:
+        A = blocks(None if lvl == 0 else perm[a:b], cols)
     J, P, ident = column_id(A, tol)
     return lvl, q, cols[J], P, ident
 
@@ -42,16 +46,26 @@ def _init_worker():
         pass
 
 
+def _cost(task):
+    """Rough flop count of a task's ID (the QR of a rows x cols block)."""
+    _, _, a, b, cols = task
+    k = cols.size
+    return (b - a) * k * k + k ** 3
+
+
 def _run(tasks, workers):
-    """Yield the ID of every task (in completion order when parallel)."""
+    """Yield the ID of every task (in completion order when parallel).  A
+    parallel level hands the tasks out one at a time, most expensive first, so
+    the level does not wait on a long task started last."""
     if workers <= 1:
         for t in tasks:
             yield _id_task(t)
         return
     import multiprocessing as mp
     ctx = mp.get_context("fork")
+    order = sorted(tasks, key=_cost, reverse=True)
     with ctx.Pool(workers, initializer=_init_worker) as pool:
-        yield from pool.imap_unordered(_id_task, tasks, chunksize=max(1, len(tasks) // (8 * workers)))
+        yield from pool.imap_unordered(_id_task, order, chunksize=1)
 
 
 def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=None):
@@ -62,7 +76,8 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
     perm_x = np.asarray(perm_x, dtype=np.int32)
     xoff = np.asarray(xoff, dtype=np.int64)
     koff = np.asarray(koff, dtype=np.int64)
-    _CTX.update(blocks=blocks, perm=perm_x, tol=float(tol))
+    tree = blocks.tree_ordered(perm_x) if hasattr(blocks, "tree_ordered") else None
+    _CTX.update(blocks=blocks, perm=perm_x, tol=float(tol), tree=tree)
     rank = np.zeros((L + 1, nb), dtype=np.int32)
     ident = np.zeros((L + 1, nb), dtype=np.uint8)
     P_blocks = [[None] * nb for _ in range(L + 1)]
@@ -107,7 +122,8 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
         rows = perm_x[xoff[i]:xoff[i + 1]]
         cols = J_prev[i]
         if rows.size and cols.size:
-            U_list.append(np.ascontiguousarray(blocks(rows, cols)))
+            U = tree(int(xoff[i]), int(xoff[i + 1]), cols) if tree is not None else blocks(rows, cols)
+            U_list.append(np.ascontiguousarray(U))
         else:
             U_list.append(np.zeros((rows.size, cols.size)))
     # Pack the blocks into one array each, releasing every block once it is

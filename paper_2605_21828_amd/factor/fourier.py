@@ -80,6 +80,18 @@ class FourierBlocks:
                 out[s:s + chunk, r] = np.einsum("ja,ja->j", self.tab[0][s:s + chunk], self.tab[1][s:s + chunk] @ G.T)
         return out[:, 0] if vec else out
 
+    def tree_ordered(self, perm):
+        """(a, b, cols) -> Phi[perm[a:b]][:, cols], from copies of the tables with
+        their rows in the order perm, so a range of positions is a row slice."""
+        perm = np.asarray(perm)
+        t0, t1 = self.tab[0][perm], self.tab[1][perm]
+        c1, c2 = self.c1, self.c2
+
+        def block(a, b, cols):
+            cols = np.asarray(cols)
+            return t0[a:b][:, c1[cols]] * t1[a:b][:, c2[cols]]
+        return block
+
     def __call__(self, rows, cols):
         """Phi[rows][:, cols]; rows=None selects every point."""
         cols = np.asarray(cols)

@@ -15,7 +15,7 @@ phi_2 <= 0 go to the first part) then puts x_a <= mid in the first child.  On
 the flat periodic square the Fiedler vector itself is degenerate (cos x1, sin x1,
 cos x2, sin x2 share one eigenvalue), so the box form is used there: the root box
 is the points' bounding box, child boxes are the geometric halves, ties in side
-length go to x1.  Mesh surfaces use `mesh_fiedler_tree` in `mesh.py`.
+length go to x1.  Mesh surfaces use `mesh_fiedler_tree` in `mesh_tree.py`.
 
 Frequency tree.  A binary tree on the eigenvalue-sorted column range (Sec. 3,
 first paragraph: a tree on [0, lambda_m]); by index rather than by eigenvalue
