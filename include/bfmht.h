@@ -228,6 +228,24 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
                                  const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
                                  int32_t transpose, void *ws, int64_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bfmht_apply with its
+ * workspace taken from a fixed device array that the library holds, so the
+ * call takes no workspace argument and allocates nothing.  Every GPU the
+ * library runs on holds its own array of BFMHT_NOALLOC_WORKSPACE_BYTES from
+ * the first use of the library's device code there until the process ends;
+ * its device address is resolved once per device, on this call's first use
+ * there (the stream's device; the current device for the NULL stream).
+ * Otherwise as bfmht_apply: f = Phi~ c, asynchronous on `stream`, same
+ * operands and errors.  ENOSPACE, with nothing launched, when
+ * bfmht_workspace_bytes(plan, nrhs) exceeds the array.  All calls on one GPU
+ * share its array (the last call's level vectors stay there; no part of it
+ * needs clearing), so calls that overlap on one GPU (different streams, or
+ * different host threads) race: serialise them. */
+#define BFMHT_NOALLOC_WORKSPACE_BYTES (256ll << 20)
+bfmht_status bfmht_apply_noalloc(const bfmht_plan *plan, const void *c, int64_t ldc, void *f, int64_t ldf,
+                                 int32_t nrhs, void *stream);
+
 /* Free the plan's host memory.  Does not touch device memory.  NULL is a no-op. */
 void bfmht_plan_destroy(bfmht_plan *plan);
 

@@ -42,8 +42,10 @@ EXPORTED = [
     "bfmht_plan_num_stages", "bfmht_plan_set_tile", "bfmht_plan_get_tile",
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
     "bfmht_apply_scaled", "bfmht_apply_transpose_scaled", "bfmht_lsqr", "bfmht_lsqr_workspace_bytes",
-    "bfmht_plan_create_ex", "bfmht_plan_stored_entries",
+    "bfmht_plan_create_ex", "bfmht_plan_stored_entries", "bfmht_apply_noalloc",
 ]
+
+NOALLOC_WORKSPACE_BYTES = 256 << 20  # BFMHT_NOALLOC_WORKSPACE_BYTES
 
 PLAN_FULL_BLOCKS = 1  # plan flag: keep every ID block as the full P (no compact forward form)
 
@@ -70,6 +72,8 @@ def load_library(path=LIB_PATH):
     lib.bfmht_apply.restype = ctypes.c_int
     lib.bfmht_apply_transpose.argtypes = [vp, vp, i64, vp, i64, i32, vp, i64, vp]
     lib.bfmht_apply_transpose.restype = ctypes.c_int
+    lib.bfmht_apply_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, vp]
+    lib.bfmht_apply_noalloc.restype = ctypes.c_int
     lib.bfmht_apply_scaled.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
     lib.bfmht_apply_scaled.restype = ctypes.c_int
     lib.bfmht_apply_transpose_scaled.argtypes = [vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
@@ -172,6 +176,10 @@ def bfmht_plan_upload(plan, dev_ptr, dev_bytes, stream=0):
 
 def bfmht_apply(plan, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream=0):
     _check(lib.bfmht_apply(plan, c_ptr, ldc, f_ptr, ldf, nrhs, ws_ptr, ws_bytes, stream), "bfmht_apply")
+
+
+def bfmht_apply_noalloc(plan, c_ptr, ldc, f_ptr, ldf, nrhs, stream=0):
+    _check(lib.bfmht_apply_noalloc(plan, c_ptr, ldc, f_ptr, ldf, nrhs, stream), "bfmht_apply_noalloc")
 
 
 def bfmht_apply_transpose(plan, f_ptr, ldf, g_ptr, ldg, nrhs, ws_ptr, ws_bytes, stream=0):

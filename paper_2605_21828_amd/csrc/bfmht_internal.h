@@ -19,7 +19,18 @@
 #pragma once
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/bfmht.h"
+
 namespace bfmht {
+
+// Host side of the C ABI (plan.cpp): record the calling thread's error message
+// and return s; one single apply of plan p (forward or transposed) with the two
+// level buffers in ws (checked like bfmht_apply's workspace).
+bfmht_status set_error(bfmht_status s, const std::string &msg);
+bfmht_status apply_with_workspace(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out,
+                                  int64_t ldout, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream);
 
 // One forward GEMM job: dst rows = W (M x K, row stride ldw) * src rows.
 // A column interpolative decomposition P = [I T] Pi^T keeps, for every output

@@ -794,6 +794,17 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
 
 }  // namespace
 
+namespace bfmht {
+
+bfmht_status set_error(bfmht_status s, const std::string &msg) { return fail(s, msg); }
+
+bfmht_status apply_with_workspace(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out,
+                                  int64_t ldout, int32_t nrhs, void *ws, int64_t ws_bytes, void *stream) {
+  return run_apply(p, fwd, in, ldin, out, ldout, nrhs, ws, ws_bytes, stream);
+}
+
+}  // namespace bfmht
+
 extern "C" {
 
 bfmht_status bfmht_apply(const bfmht_plan *p, const void *c, int64_t ldc, void *f, int64_t ldf, int32_t nrhs,
