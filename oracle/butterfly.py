@@ -17,8 +17,15 @@ for l = 1..L, then f[tau_i] = U_i y_Li0.  The paper's prose lists the apply
 steps in the adjoint's order; this follows the algebra of the recursion.  The
 analysis is the exact transpose of those steps.
 
+The same recursion holds for k-ary trees (Sec. 2: the construction generalizes
+to k-ary trees, quadtrees in two dimensions; Sec. 5 analyses the quadtree in
+space with a 4-ary tree on the eigenvalue range): a node's k children
+c_1 .. c_k replace the pair, so y_lij = P_lij [y_{l-1,p,kj}; ...; y_{l-1,p,kj+k-1}]
+with p the parent of tau_i.  A factor set states its k as "arity" (2 if absent).
+
 Factor-set fields (plain dict of NumPy arrays, the factor-file schema):
-  n, m, L        sizes; both trees are complete binary trees of depth L
+  n, m, L        sizes; both trees are complete k-ary trees of depth L
+  arity          k (optional, default 2); below, 2^ stands for k^
   perm_x  [n]    tree position -> original point index
   xoff    [2^L+1] space-leaf offsets into tree positions
   koff    [2^L+1] frequency-leaf offsets into the eigenvalue-sorted columns
@@ -31,25 +38,30 @@ Factor-set fields (plain dict of NumPy arrays, the factor-file schema):
 import numpy as np
 
 
-def _children(L, lvl, i, j):
-    """Previous-level block ids of the two inputs of block (lvl, i, j).
+def arity(fs):
+    """Children per tree node (k of a k-ary tree; 2 when the set does not say)."""
+    return int(fs["arity"]) if "arity" in fs else 2
 
-    The parent p of space node i and the children 2j, 2j+1 of frequency node j
-    (Sec. 2, local labels p, c1, c2), as space-major ids at level lvl - 1.
+
+def _children(L, lvl, i, j, k=2):
+    """Previous-level block ids of the k inputs of block (lvl, i, j).
+
+    The parent p of space node i and the children k j, ..., k j + k - 1 of
+    frequency node j (Sec. 2, local labels p, c1, c2 for k = 2), as space-major
+    ids at level lvl - 1.
     """
-    nf_prev = 1 << (L - lvl + 1)
-    p = i >> 1
-    return p * nf_prev + 2 * j, p * nf_prev + 2 * j + 1
+    nf_prev = k ** (L - lvl + 1)
+    p = i // k
+    return [p * nf_prev + k * j + t for t in range(k)]
 
 
 def _block_in_rows(fs, lvl, q):
     """Number of input rows of block q at level lvl."""
-    L = int(fs["L"])
+    L, k = int(fs["L"]), arity(fs)
     if lvl == 0:
         return int(fs["koff"][q + 1] - fs["koff"][q])
-    i, j = divmod(q, 1 << (L - lvl))
-    q1, q2 = _children(L, lvl, i, j)
-    return int(fs["rank"][lvl - 1][q1] + fs["rank"][lvl - 1][q2])
+    i, j = divmod(q, k ** (L - lvl))
+    return int(sum(fs["rank"][lvl - 1][c] for c in _children(L, lvl, i, j, k)))
 
 
 def _P(fs, lvl, q):
@@ -62,7 +74,7 @@ def _P(fs, lvl, q):
 
 
 def _U(fs, i):
-    L = int(fs["L"])
+    L = int(fs["L"])  # leaf i of the space tree
     rows = int(fs["xoff"][i + 1] - fs["xoff"][i])
     r = int(fs["rank"][L][i])
     o = int(fs["U_off"][i])
@@ -75,18 +87,17 @@ def apply(fs, c):
     squeeze = c.ndim == 1
     if squeeze:
         c = c[:, None]
-    L, n = int(fs["L"]), int(fs["n"])
-    nb = 1 << L
+    L, n, k = int(fs["L"]), int(fs["n"]), arity(fs)
+    nb = k ** L
     koff, xoff, perm = fs["koff"], fs["xoff"], fs["perm_x"]
     # level 0: one block per frequency leaf
     y = [_P(fs, 0, j) @ c[koff[j]:koff[j + 1]] for j in range(nb)]
     for lvl in range(1, L + 1):
-        nf = 1 << (L - lvl)
+        nf = k ** (L - lvl)
         ynew = []
-        for i in range(1 << lvl):
+        for i in range(k ** lvl):
             for j in range(nf):
-                q1, q2 = _children(L, lvl, i, j)
-                x = np.vstack([y[q1], y[q2]])
+                x = np.vstack([y[q] for q in _children(L, lvl, i, j, k)])
                 ynew.append(_P(fs, lvl, i * nf + j) @ x)
         y = ynew
     f = np.zeros((n, c.shape[1]), dtype=np.float64)
@@ -101,21 +112,22 @@ def apply_transpose(fs, f):
     squeeze = f.ndim == 1
     if squeeze:
         f = f[:, None]
-    L, m = int(fs["L"]), int(fs["m"])
-    nb = 1 << L
+    L, m, k = int(fs["L"]), int(fs["m"]), arity(fs)
+    nb = k ** L
     b = f.shape[1]
     koff, xoff, perm = fs["koff"], fs["xoff"], fs["perm_x"]
     z = [_U(fs, i).T @ f[perm[xoff[i]:xoff[i + 1]]] for i in range(nb)]
     for lvl in range(L, 0, -1):
-        nf = 1 << (L - lvl)
+        nf = k ** (L - lvl)
         zprev = [np.zeros((int(fs["rank"][lvl - 1][q]), b)) for q in range(nb)]
-        for i in range(1 << lvl):
+        for i in range(k ** lvl):
             for j in range(nf):
-                q1, q2 = _children(L, lvl, i, j)
                 w = _P(fs, lvl, i * nf + j).T @ z[i * nf + j]
-                r1 = zprev[q1].shape[0]
-                zprev[q1] += w[:r1]
-                zprev[q2] += w[r1:]
+                s = 0
+                for q in _children(L, lvl, i, j, k):   # split the stacked rows back to the children
+                    r = zprev[q].shape[0]
+                    zprev[q] += w[s:s + r]
+                    s += r
         z = zprev
     g = np.zeros((m, b), dtype=np.float64)
     for j in range(nb):
@@ -125,12 +137,12 @@ def apply_transpose(fs, f):
 
 def stored_entries(fs):
     """F: number of stored factor entries (identity blocks store nothing)."""
-    L = int(fs["L"])
+    L, k = int(fs["L"]), arity(fs)
     tot = 0
     for lvl in range(L + 1):
-        for q in range(1 << L):
+        for q in range(k ** L):
             if not fs["ident"][lvl][q]:
                 tot += int(fs["rank"][lvl][q]) * _block_in_rows(fs, lvl, q)
-    for i in range(1 << L):
+    for i in range(k ** L):
         tot += int(fs["xoff"][i + 1] - fs["xoff"][i]) * int(fs["rank"][L][i])
     return tot

@@ -10,7 +10,8 @@ module assembles those matrices densely (tiny sizes only) and multiplies them:
 where B_0 maps coefficients to the stacked level-0 vector, B_l maps the stacked
 level-(l-1) vector to the stacked level-l vector, and B_final scatters the leaf
 bases U_i into the point rows.  It is a second, independent formulation of what
-the butterfly apply computes, used to pin the recursive apply.
+the butterfly apply computes, used to pin the recursive apply.  Factor sets of k-ary trees ("arity" k, 2 if absent) are
+assembled the same way, each block reading its k children.
 """
 import numpy as np
 
@@ -22,7 +23,8 @@ def _offsets(ranks):
 def dense_operator(fs):
     """The explicit n x m matrix Phi~ represented by the factor set (tiny sizes)."""
     L, n, m = int(fs["L"]), int(fs["n"]), int(fs["m"])
-    nb = 1 << L
+    k = int(fs["arity"]) if "arity" in fs else 2
+    nb = k ** L
     rank = np.asarray(fs["rank"])
     ident = np.asarray(fs["ident"])
     koff = np.asarray(fs["koff"])
@@ -41,16 +43,16 @@ def dense_operator(fs):
     mats.append(B)
     prev_off = off0
     for lvl in range(1, L + 1):
-        nf = 1 << (L - lvl)
+        nf = k ** (L - lvl)
         cur_off = _offsets(rank[lvl])
         B = np.zeros((cur_off[-1], prev_off[-1]))
-        for i in range(1 << lvl):
+        for i in range(k ** lvl):
             for j in range(nf):
                 q = i * nf + j
-                c1 = (i // 2) * (2 * nf) + 2 * j   # first child block at the previous level
-                c2 = c1 + 1
-                cols = list(range(prev_off[c1], prev_off[c1 + 1])) + \
-                    list(range(prev_off[c2], prev_off[c2 + 1]))
+                c1 = (i // k) * (k * nf) + k * j   # first child block at the previous level
+                cols = []
+                for c in range(c1, c1 + k):
+                    cols += list(range(prev_off[c], prev_off[c + 1]))
                 r = rank[lvl][q]
                 if ident[lvl][q]:
                     blk = np.eye(r, len(cols))

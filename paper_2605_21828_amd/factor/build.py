@@ -68,11 +68,14 @@ def _run(tasks, workers):
         yield from pool.imap_unordered(_id_task, order, chunksize=1)
 
 
-def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=None):
-    """Build the factor set dict (schema documented in `io.py`)."""
+def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=None, arity=2):
+    """Build the factor set dict (schema documented in `io.py`).  arity: children
+    per tree node (2, or 4 for a quadtree in space with a 4-ary frequency tree);
+    a block at level l concatenates the skeletons of its `arity` inputs."""
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
-    nb = 1 << L
+    a_ = int(arity)
+    nb = a_ ** L
     perm_x = np.asarray(perm_x, dtype=np.int32)
     xoff = np.asarray(xoff, dtype=np.int64)
     koff = np.asarray(koff, dtype=np.int64)
@@ -90,14 +93,14 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
             for j in range(nb):
                 tasks.append((0, j, 0, n, np.arange(koff[j], koff[j + 1], dtype=np.int64)))
         else:
-            nf = 1 << (L - lvl)
-            w = 1 << (L - lvl)   # leaves per space node at depth lvl
-            for i in range(1 << lvl):
+            nf = a_ ** (L - lvl)
+            w = a_ ** (L - lvl)   # leaves per space node at depth lvl
+            for i in range(a_ ** lvl):
                 a, b = int(xoff[i * w]), int(xoff[(i + 1) * w])
-                p = i >> 1
+                p = i // a_
                 for j in range(nf):
-                    q1 = p * (2 * nf) + 2 * j
-                    cols = np.concatenate([J_prev[q1], J_prev[q1 + 1]])
+                    q1 = p * (a_ * nf) + a_ * j
+                    cols = np.concatenate([J_prev[q1 + t] for t in range(a_)])
                     tasks.append((lvl, i * nf + j, a, b, cols))
         J_cur = [None] * nb
         t_note = time.time()
@@ -153,7 +156,7 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
         U_all[U_off[i]:U_off[i] + U_list[i].size] = U_list[i].ravel()
         U_list[i] = None
     return dict(
-        n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol),
+        n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol), arity=np.int64(a_),
         perm_x=perm_x, xoff=xoff, koff=koff, rank=rank, ident=ident,
         P=P_all,
         P_off=P_off,

@@ -25,10 +25,10 @@ splits at a + ceil((b - a) / 2).
 import numpy as np
 
 
-def depth_for(n, leaf):
-    """L = ceil(log2(n / leaf)), at least 0."""
+def depth_for(n, leaf, arity=2):
+    """L = ceil(log_arity(n / leaf)), at least 0."""
     L = 0
-    while (n + (1 << L) - 1) >> L > leaf:
+    while -(-n // arity ** L) > leaf:
         L += 1
     return L
 
@@ -65,8 +65,54 @@ def box_bisection_tree(points, L):
     return perm.astype(np.int32), xoff
 
 
-def frequency_tree(m, L):
-    """Leaf offsets int64[2^L + 1] of the index-halving tree on [0, m)."""
+def quadtree(points, L):
+    """Quadtree of fixed depth L on 2-D points (Sec. 2: the construction
+    generalizes to quadtrees; Sec. 5 uses one on [-pi, pi]^2).  A box's four
+    children are its quadrants, split at the midpoints of both sides, in the
+    order (x1 low, x2 low), (x1 low, x2 high), (x1 high, x2 low), (x1 high, x2
+    high); a coordinate equal to the midpoint goes low, as in the binary
+    Neumann-box tree.  The root box is the points' bounding box.
+
+    Returns (perm_x int32[n], xoff int64[4^L + 1]) like box_bisection_tree.
+    """
+    pts = np.asarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    lo = pts.min(axis=0) if n else np.zeros(2)
+    hi = pts.max(axis=0) if n else np.zeros(2)
+    nodes = [(np.arange(n, dtype=np.int64), lo.copy(), hi.copy())]
+    for _ in range(L):
+        nxt = []
+        for idx, blo, bhi in nodes:
+            mid = 0.5 * (blo + bhi)
+            low1 = pts[idx, 0] <= mid[0]
+            low2 = pts[idx, 1] <= mid[1]
+            for h1 in (0, 1):
+                for h2 in (0, 1):
+                    sel = (low1 != bool(h1)) & (low2 != bool(h2))
+                    clo, chi = blo.copy(), bhi.copy()
+                    if h1:
+                        clo[0] = mid[0]
+                    else:
+                        chi[0] = mid[0]
+                    if h2:
+                        clo[1] = mid[1]
+                    else:
+                        chi[1] = mid[1]
+                    nxt.append((idx[sel], clo, chi))
+        nodes = nxt
+    perm = np.concatenate([nd[0] for nd in nodes]) if nodes else np.zeros(0, np.int64)
+    sizes = np.array([len(nd[0]) for nd in nodes], dtype=np.int64)
+    xoff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return perm.astype(np.int32), xoff
+
+
+def frequency_tree(m, L, arity=2):
+    """Leaf offsets int64[arity^L + 1] of the index-splitting tree on [0, m).
+    A node's range [a, b) is halved at a + ceil((b - a) / 2); a 4-ary node
+    halves twice, so its four children are the binary tree's grandchildren."""
+    if arity not in (2, 4):
+        raise ValueError("arity must be 2 or 4")
+    L = L * (1 if arity == 2 else 2)
     ranges = [(0, m)]
     for _ in range(L):
         nxt = []
@@ -78,7 +124,7 @@ def frequency_tree(m, L):
     return np.array([r[0] for r in ranges] + [m], dtype=np.int64)
 
 
-def node_range(off, L, depth, idx):
+def node_range(off, L, depth, idx, arity=2):
     """[start, end) of node idx at the given depth, from leaf offsets of a depth-L tree."""
-    w = 1 << (L - depth)
+    w = arity ** (L - depth)
     return int(off[idx * w]), int(off[(idx + 1) * w])

@@ -19,14 +19,16 @@ def _partition(rng, total, parts, allow_empty=True):
 
 
 def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=True, identity_values=False,
-                      p_id_form=0.0, ident_levels=0):
+                      p_id_form=0.0, ident_levels=0, arity=2):
     """Random factor set.  identity_values=True makes every P the identity and
     every U_i a 0/1 selection so that the apply is an exact permutation.
     p_id_form: probability that a non-identity block with 0 < rank < inputs has
     the column-ID form P = [I T] Pi^T (r random columns hold e_1 .. e_r).
-    ident_levels: levels 0 .. ident_levels-1 hold identity blocks only."""
+    ident_levels: levels 0 .. ident_levels-1 hold identity blocks only.
+    arity: children per tree node (k-ary trees); a block's inputs are the k
+    children of its frequency node under the parent of its space node."""
     rng = np.random.default_rng(seed)
-    nb = 1 << L
+    nb = arity ** L
     perm = rng.permutation(n).astype(np.int32)
     xoff = _partition(rng, n, nb, allow_empty)
     koff = _partition(rng, m, nb, allow_empty)
@@ -35,14 +37,14 @@ def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=Tr
     P_off = np.full((L + 1, nb), -1, np.int64)
     chunks, off = [], 0
     for lvl in range(L + 1):
-        nf = 1 << (L - lvl)
+        nf = arity ** (L - lvl)
         for q in range(nb):
             if lvl == 0:
                 rin = int(koff[q + 1] - koff[q])
             else:
                 i, j = divmod(q, nf)
-                q1 = (i >> 1) * 2 * nf + 2 * j
-                rin = int(rank[lvl - 1, q1] + rank[lvl - 1, q1 + 1])
+                q1 = (i // arity) * arity * nf + arity * j
+                rin = int(rank[lvl - 1, q1:q1 + arity].sum())
             if identity_values or lvl < ident_levels or (rng.random() < p_ident and (max_rank is None or rin <= max_rank)):
                 rank[lvl, q] = rin
                 ident[lvl, q] = 1
@@ -74,7 +76,7 @@ def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=Tr
         U_off[i] = uo
         uch.append(blk.ravel())
         uo += blk.size
-    return dict(n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(0.0),
+    return dict(n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(0.0), arity=np.int64(arity),
                 perm_x=perm, xoff=xoff, koff=koff, rank=rank, ident=ident,
                 P=np.concatenate(chunks) if chunks else np.zeros(0), P_off=P_off,
                 U=np.concatenate(uch) if uch else np.zeros(0), U_off=U_off)

@@ -81,3 +81,26 @@ def test_parallel_build_equals_serial_build():
     fs2, _ = fio.fourier_factors(pts, 256, 32, 1e-8, workers=3, cache=False)
     for key in ("rank", "ident", "P", "P_off", "U", "U_off", "skel_L"):
         assert np.array_equal(fs1[key], fs2[key]), key
+
+
+def test_quadtree_is_a_partition_into_quadrants():
+    """Quadtree on the 16 x 16 grid: a permutation, 4^2 leaves of 16 points each,
+    every leaf inside its quadrant box, and its leaves are the binary Neumann-box
+    tree's leaves at twice the depth (square boxes alternate the split axis)."""
+    import numpy as np
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.factor.trees import box_bisection_tree, frequency_tree, quadtree
+    pts = wl.grid_points(16)
+    perm, xoff = quadtree(pts, 2)
+    assert sorted(perm.tolist()) == list(range(256))
+    assert np.array_equal(np.diff(xoff), np.full(16, 16))
+    perm2, xoff2 = box_bisection_tree(pts, 4)
+    assert np.array_equal(xoff, xoff2)
+    for i in range(16):
+        assert set(perm[xoff[i]:xoff[i + 1]].tolist()) == set(perm2[xoff2[i]:xoff2[i + 1]].tolist())
+    rng = np.random.default_rng(3)
+    iid = rng.uniform(-np.pi, np.pi, (1000, 2))
+    p3, x3 = quadtree(iid, 3)
+    assert sorted(p3.tolist()) == list(range(1000)) and x3[-1] == 1000 and len(x3) == 65
+    # 4-ary frequency leaves are the binary index tree's leaves at twice the depth
+    assert np.array_equal(frequency_tree(1000, 3, 4), frequency_tree(1000, 6))

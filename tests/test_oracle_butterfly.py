@@ -123,7 +123,7 @@ def test_mutant_swapped_children_fails(monkeypatch):
     fs = random_factor_set(21, 64, 64, 3, max_rank=10, p_ident=0.0)
     A = osp.dense_operator(fs)
     orig = ob._children
-    _planted(monkeypatch, "_children", lambda L, lvl, i, j: orig(L, lvl, i, j)[::-1])
+    _planted(monkeypatch, "_children", lambda L, lvl, i, j, k=2: orig(L, lvl, i, j, k)[::-1])
     try:
         got = ob.apply(fs, np.eye(64))
     except ValueError:
@@ -135,7 +135,7 @@ def test_mutant_wrong_parent_fails(monkeypatch):
     fs = random_factor_set(22, 64, 64, 3, max_rank=10, p_ident=0.0)
     A = osp.dense_operator(fs)
     orig = ob._children
-    _planted(monkeypatch, "_children", lambda L, lvl, i, j: orig(L, lvl, i ^ 2 if i >= 2 else i, j))
+    _planted(monkeypatch, "_children", lambda L, lvl, i, j, k=2: orig(L, lvl, i ^ 2 if i >= 2 else i, j, k))
     try:
         got = ob.apply(fs, np.eye(64))
     except ValueError:
@@ -163,3 +163,54 @@ def test_mutant_dropped_transfer_term_fails(monkeypatch, exact_small):
     _planted(monkeypatch, "_P", bad)
     c = np.random.default_rng(2).standard_normal(Phi.shape[1])
     assert np.linalg.norm(ob.apply(fs, c) - Phi @ c) > 1e-6 * np.linalg.norm(Phi @ c)
+
+
+# ---- k-ary trees (Sec. 2: the construction generalizes to k-ary trees; Sec. 5:
+# quadtree in space, 4-ary tree on the eigenvalues) ----
+
+def test_quadtree_tol0_apply_equals_dense_and_dft():
+    """A 4-ary factor set built at tolerance 0 reproduces the transform: the
+    dense product and, on the grid, the inverse DFT."""
+    pts = om.uniform_grid(32)
+    fs, _ = fio.fourier_factors(pts, 256, 16, 0.0, workers=1, cache=False, arity=4)
+    assert int(fs["arity"]) == 4 and int(fs["L"]) == 3
+    assert fs["ident"].sum() < fs["ident"].size and fs["P"].size > 0
+    Phi = om.phi(pts, om.fourier_modes(256))
+    rng = np.random.default_rng(21)
+    c = rng.standard_normal((256, 3))
+    f = rng.standard_normal((1024, 3))
+    assert np.linalg.norm(ob.apply(fs, c) - Phi @ c) <= 1e-12 * np.linalg.norm(Phi @ c)
+    assert np.linalg.norm(ob.apply_transpose(fs, f) - Phi.T @ f) <= 1e-12 * np.linalg.norm(Phi.T @ f)
+    ref = om.grid_synthesis_ifft2(32, om.fourier_modes(256), c)
+    assert np.linalg.norm(ob.apply(fs, c) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("seed,n,m,L", [(30, 40, 24, 1), (31, 70, 64, 2), (32, 200, 90, 2), (33, 17, 5, 2)])
+def test_quadtree_apply_equals_sparse_product(seed, n, m, L):
+    fs = random_factor_set(seed, n, m, L, max_rank=12, arity=4)
+    A = osp.dense_operator(fs)
+    assert np.allclose(ob.apply(fs, np.eye(m)), A, atol=1e-12, rtol=1e-12)
+    assert np.allclose(ob.apply_transpose(fs, np.eye(n)), A.T, atol=1e-12, rtol=1e-12)
+
+
+def test_quadtree_adjoint_identity_and_error_tracks_tolerance():
+    fs = random_factor_set(34, 300, 120, 2, max_rank=16, arity=4)
+    rng = np.random.default_rng(34)
+    c, f = rng.standard_normal((120, 2)), rng.standard_normal((300, 2))
+    lhs, rhs = np.sum(ob.apply(fs, c) * f), np.sum(c * ob.apply_transpose(fs, f))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+    pts = rng.uniform(-np.pi, np.pi, (4096, 2))
+    fq, _ = fio.fourier_factors(pts, 512, 32, 1e-8, workers=1, cache=False, arity=4)
+    Phi = om.phi(pts, om.fourier_modes(512))
+    c1 = rng.standard_normal(512)
+    err = np.linalg.norm(ob.apply(fq, c1) - Phi @ c1) / np.linalg.norm(Phi @ c1)
+    assert 1e-5 * 1e-8 < err < 30 * 1e-8
+
+
+def test_quadtree_mutant_swapped_children_fails(monkeypatch):
+    """Reversing the order of a block's four inputs is caught by the sparse product."""
+    fs = random_factor_set(35, 70, 64, 2, max_rank=12, arity=4)
+    A = osp.dense_operator(fs)
+    orig = ob._children
+    _planted(monkeypatch, "_children", lambda L, lvl, i, j, k=2: orig(L, lvl, i, j, k)[::-1])
+    assert not np.allclose(ob.apply(fs, np.eye(64)), A, atol=1e-9)
