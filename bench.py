@@ -32,6 +32,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_memory():
+    """Resident size of this process and the host memory still available, GB."""
+    try:
+        import psutil
+        return {"rss_GB": round(psutil.Process().memory_info().rss / 1e9, 1),
+                "avail_GB": round(psutil.virtual_memory().available / 1e9, 1)}
+    except Exception:
+        return {}
+
+
 def measured_traffic(workload):
     """HBM bytes per forward FP32 stage launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or
@@ -71,7 +81,8 @@ def measured_mfma_busy(workload):
 MFMA_PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
 HBM_PEAK = 8000.0
 SPLIT_PRODUCTS = {"f64": 1, "f32": 1, "bf16x2": 3, "bf16x3": 6}
-FACTOR_BYTES = {"f64": 8, "f32": 4, "bf16x2": 4, "bf16x3": 6}
+# factor bytes streamed per stored entry: the split precisions keep FP32 factors and split them on load
+FACTOR_BYTES = {"f64": 8, "f32": 4, "bf16x2": 4, "bf16x3": 4}
 
 
 def roofline_for(prec, F, n, m, b, apply_ms, launches):
@@ -175,6 +186,38 @@ def cpu_baseline(fs, pts, c_host, f_host, out32, g32, rows, cols, lam, variant_o
     return base, acc
 
 
+def dense_context(pts, modes, c32, f32, reps, torch):
+    """Context only: the same products with the dense transform matrix formed on
+    the GPU (closed-form Fourier entries) and multiplied by the vendor GEMM
+    (torch.matmul: rocBLAS / hipBLASLt), FP64 and FP32, both directions.  Not a
+    path of this library; it shows what the butterfly saves at this size."""
+    dev = c32.device
+    x = torch.tensor(pts, dtype=torch.float64, device=dev)
+    md = torch.tensor(modes, dtype=torch.int64, device=dev)
+    kmax = int(md[:, :2].max())
+    k = torch.arange(kmax + 1, dtype=torch.float64, device=dev)
+    tabs = []
+    for a in range(2):
+        arg = x[:, a:a + 1] * k[None, :]
+        tabs.append(torch.stack([torch.cos(arg), torch.sin(arg)], dim=2).reshape(x.shape[0], -1))
+    Phi = tabs[0][:, 2 * md[:, 0] + md[:, 2]] * tabs[1][:, 2 * md[:, 1] + md[:, 3]]
+    del tabs
+    out = {"dense_GB_fp64": Phi.numel() * 8 / 1e9}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        A = Phi if dt == torch.float64 else Phi.float()
+        c, f = c32.to(dt), f32.to(dt)
+        ft = f.t().contiguous()
+        A @ c
+        torch.matmul(ft, A)
+        out[name + "_apply_ms"] = event_time(lambda: A @ c, reps, torch)
+        out[name + "_apply_transpose_ms"] = event_time(lambda: torch.matmul(ft, A), reps, torch)
+        del A, c, f, ft
+    del Phi
+    torch.cuda.empty_cache()
+    out["note"] = "dense Phi formed on the GPU, vendor GEMM via torch.matmul; context only, not this library"
+    return out
+
+
 def bench_batched(args):
     """Multi-instance workload: 32 uniform-grid instances of uneven size, FP32."""
     import torch
@@ -244,8 +287,9 @@ def bench_batched(args):
     frac = t_roof / (ms_fwd * 1e-3)
     bound = "mfma" if t_mfma >= t_hbm else "hbm"
     peak = MFMA_PEAK["f32"] if bound == "mfma" else HBM_PEAK
-    errs = None
+    errs, base = None, None
     if not args.no_cpu_baseline:
+        from oracle import butterfly as ob
         from oracle import dense as od
         from oracle import modes as om
         errs = []
@@ -253,6 +297,21 @@ def bench_batched(args):
         for (side, b), y, c in zip(inst, outs, cs_host):
             ref = om.grid_synthesis_ifft2(side, om.fourier_modes(side * side // 4), c)
             errs.append(od.rel_err_cols(y.double().cpu().numpy(), ref)[0])
+        # the oracle's butterfly apply + transpose of every instance, whole
+        # passes over the batch, bounded to about 15 s of host work
+        fvs_host = [fv.double().cpu().numpy() for fv in fvs]
+        t0 = time.time()
+        passes = done = 0
+        while passes == 0 or (time.time() - t0 < 15.0 and passes < 8):
+            for (side, b), c, fv in zip(inst, cs_host, fvs_host):
+                ob.apply(built[side], c)
+                ob.apply_transpose(built[side], fv)
+                done += side * side * b
+            passes += 1
+        dt_cpu = time.time() - t0
+        base = {"value": 2.0 * done / dt_cpu, "unit": "RHS*points/s", "cores": _blas_threads(), "kind": "oracle",
+                "sample": "oracle butterfly apply + transpose (NumPy FP64) of every instance's factors and RHS, "
+                          "%d pass(es) over the 32 instances, %.1f s" % (passes, dt_cpu)}
     res = {
         "metric": "butterfly apply RHS*points/s (FP32 batched synthesis + analysis)",
         "value": 2.0 * rhs_points / (ms * 1e-3), "unit": "RHS*points/s",
@@ -267,9 +326,10 @@ def bench_batched(args):
                      "note": "sum over instances of max(HBM time, MFMA time); achieved = frac x peak of the "
                              "dominant bound",
                      "kernel": "batched_stage_kernel<1> (all launches of one batched FP32 apply)"},
-        "cpu_baseline": None,
+        "cpu_baseline": base,
         "extra": {"batched_apply_ms": ms_fwd, "one_by_one_apply_ms": ms_seq,
-                  "batching_speedup": ms_seq / ms_fwd, "max_instance_rel_err_vs_inverse_dft":
+                  "batching_speedup": ms_seq / ms_fwd,
+                  "max_instance_rel_err_vs_inverse_dft":
                   max(errs) if errs else None, "instance_rel_err": errs},
     }
     print(json.dumps(res), flush=True)
@@ -418,10 +478,11 @@ def bench_lsq(args):
     w = wl.WORKLOADS["iid" + args.workload[len("lsq"):]]
     n, m, wid = w["n"], w["m"], w["wid"]
     pts = wl.points_for(w)
-    log("building factors: n=%d m=%d leaf=%d tol=%g" % (n, m, w["leaf"], w["tol"]))
+    log("building factors: n=%d m=%d leaf=%d tol=%g workers=%d" % (n, m, w["leaf"], w["tol"], args.workers),
+        host_memory())
     t0 = time.time()
     fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
-                                log=lambda s: log("  factor", s))
+                                log=lambda s: log("  factor", s, host_memory()))
     t_build = time.time() - t0
     F = fio.stored_entries(fs)
     modes = real_modes(m)
@@ -430,8 +491,11 @@ def bench_lsq(args):
     log("exact right-hand side f = Phi c* + 1e-3 noise")
     f = FourierBlocks(pts, modes).synthesis(c_star) + 1e-3 * wl.values(wid, n, 1)[:, 0]
     dev = torch.device("cuda:0")
-    log("uploading FP32 plan (%d stored entries)" % F)
+    log("uploading FP32 plan (%d stored entries)" % F, host_memory())
+    t_plan = time.time()
     plan = Plan(fs, "f32", max_nrhs=1, device=dev)
+    t_plan = time.time() - t_plan
+    log("plan created and uploaded in %.1f s" % t_plan, host_memory())
     ft = torch.tensor(f, dtype=torch.float32, device=dev)
     # step size 0.5 / sigma_max^2, sigma_max^2 from 20 power iterations on Phi~^T Phi~
     v = torch.tensor(wl.coefficients(wid, m, 1, stream=5)[:, 0], dtype=torch.float32, device=dev)
@@ -482,6 +546,7 @@ def bench_lsq(args):
         "roofline": roof,
         "cpu_baseline": base,
         "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "host_build_seconds": t_build,
+                  "plan_create_upload_seconds": t_plan, "host_memory_at_end": host_memory(),
                   "fp32_apply_ms": ms_fwd, "fp32_apply_transpose_ms": ms_bwd, "step_size": lr,
                   "loss_first": losses[0], "loss_last": losses[-1],
                   "loss_monotone": all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:])), **acc},
@@ -606,11 +671,21 @@ def bench_latency(args):
                      "graph_apply_us": graph_f * 1e3, "graph_apply_transpose_us": graph_b * 1e3}
         log("%s: apply %.1f us (graph %.1f), transpose %.1f us (graph %.1f)" % (
             prec, eager_f * 1e3, graph_f * 1e3, eager_b * 1e3, graph_b * 1e3))
-    checks = None
+    checks, base = None, None
     if not args.no_cpu_baseline:
         from oracle import butterfly as ob
         from oracle import dense as od
         from oracle import modes as om
+        # the oracle's FP64 synthesis of the same factors and RHS, bounded to about 10 s
+        t0 = time.time()
+        passes = 0
+        while passes == 0 or (time.time() - t0 < 10.0 and passes < 2000):
+            ob.apply(fs, c_host)
+            passes += 1
+        us_cpu = (time.time() - t0) * 1e6 / passes
+        base = {"value": us_cpu, "unit": "us", "cores": _blas_threads(), "kind": "oracle",
+                "sample": "oracle butterfly synthesis (NumPy FP64) of the same factors and RHS, %d pass(es), %.1f s"
+                          % (passes, us_cpu * passes * 1e-6)}
         md = om.fourier_modes(m)
         y64, g64 = outs["f64"]
         checks = {"f64_vs_oracle_butterfly": od.rel_err_cols(y64, ob.apply(fs, c_host))[0],
@@ -629,7 +704,7 @@ def bench_latency(args):
                    "L": int(fs["L"]), "step": "one apply"},
         "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2 - folded_levels(fs)),
                          note="latency-bound: the factors are L2/MALL-resident; reported, not a target"),
-        "cpu_baseline": None,
+        "cpu_baseline": base,
         "extra": {"stored_factor_entries": F, "precisions": rec, "checks": checks},
     }
     print(json.dumps(res), flush=True)
@@ -656,12 +731,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="iid65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense-context", action="store_true",
+                    help="skip the dense-matrix vendor-GEMM timing reported as context")
     ap.add_argument("--variants", default="f64,bf16x2,bf16x3",
                     help="comma list of other precisions timed on the same inputs")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile widths")
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
+    ap.add_argument("--arity", type=int, default=2, choices=(2, 4),
+                    help="tree arity of the nonuniform-square workloads (4: quadtree and 4-ary mode tree)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -689,9 +768,9 @@ def main():
     w = wl.WORKLOADS[args.workload]
     n, m, b = w["n"], w["m"], w["nrhs"]
     pts = wl.points_for(w)
-    log("building factors: n=%d m=%d leaf=%d tol=%g" % (n, m, w["leaf"], w["tol"]))
+    log("building factors: n=%d m=%d leaf=%d tol=%g arity=%d" % (n, m, w["leaf"], w["tol"], args.arity))
     fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
-                                log=lambda s: log("  factor", s))
+                                log=lambda s: log("  factor", s), arity=args.arity)
     F = fio.stored_entries(fs)
     modes = real_modes(m)
     lam = (modes[:, 0] ** 2 + modes[:, 1] ** 2).astype(np.float64)
@@ -786,6 +865,8 @@ def main():
         result_extra["speedup_fp32_vs_fp64_plain"] = ((variants_out["f64"]["apply_ms"] + variants_out["f64"]["apply_transpose_ms"])
                                                       / (ms_fwd + ms_bwd))
     result_extra["variants"] = variants_out
+    if not args.no_dense_context:
+        result_extra["dense_context"] = dense_context(pts, modes, c32, f32, reps, torch)
 
     base = None
     if not args.no_cpu_baseline:
@@ -806,7 +887,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
-                   "L": int(fs["L"]), "step": "apply + apply_transpose"},
+                   "L": int(fs["L"]), "arity": args.arity, "step": "apply + apply_transpose"},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per launch",

@@ -11,10 +11,10 @@
  * in FP64; this library only uploads and applies the factors.
  *
  * Conventions
- *  - Both trees are complete binary trees of depth L.  At level l (0..L) space
- *    node i sits at depth l and frequency node j at depth L-l; the block id is
- *    q = i * 2^(L-l) + j ("space-major").  The two inputs of block (l, i, j) are
- *    blocks (l-1, i>>1, 2j) and (l-1, i>>1, 2j+1).
+ *  - Both trees are complete binary trees of depth L (or 4-ary, see arity
+ *    below).  At level l (0..L) space node i sits at depth l and frequency node
+ *    j at depth L-l; the block id is q = i * 2^(L-l) + j ("space-major").  The
+ *    two inputs of block (l, i, j) are blocks (l-1, i>>1, 2j) and (l-1, i>>1, 2j+1).
  *  - Column bases are submatrices of Phi (column interpolative decompositions),
  *    so a block (l, i, j) computes y_lij = P_lij [y_{l-1,i>>1,2j}; y_{l-1,i>>1,2j+1}],
  *    level 0 computes y_0j = P_0j c[koff[j] : koff[j+1]], and the last stage
@@ -49,9 +49,10 @@ typedef struct bfmht_plan bfmht_plan;
  * (the plain baseline).  F32: factors and vectors in float, FP32 MFMA with
  * FP32 accumulation.  F64 and F32 applies with at most 4 right-hand sides use
  * vector FMAs instead of MFMA tiles (same jobs, same sums per output up to the
- * order of the reduction).  BF16X2 / BF16X3: factors pre-split at upload into 2 / 3
- * bfloat16 terms (hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo),
- * round to nearest even), activations split the same way per tile, BF16 MFMA
+ * order of the reduction).  BF16X2 / BF16X3: factors stored in FP32 and split
+ * into 2 / 3 bfloat16 terms as they are loaded (hi = bf16(x), lo = bf16(x - hi),
+ * lo2 = bf16(x - hi - lo), round to nearest even; 4 bytes per entry streamed),
+ * activations split the same way per tile, BF16 MFMA
  * products hi*hi + hi*lo + lo*hi (X2) or the six products whose term indices
  * sum to at most 2 (X3), FP32 accumulation, FP32 level vectors and I/O. */
 typedef enum {
@@ -72,7 +73,12 @@ typedef enum {
 /* Host FP64 factor set (Sec. 2, the factor set returned by the factorization).
  * Caller-owned; read only during bfmht_plan_create, which copies what it needs.
  *  n, m      number of points (rows of Phi) and modes (columns), m, n >= 0
- *  L         tree depth, 0 <= L <= 24
+ *  L         tree depth, arity^L <= 2^24
+ *  arity     children per tree node: 2 (binary trees), 4 (a quadtree in space
+ *            with a 4-ary frequency tree, Sec. 2's k-ary generalization, the
+ *            trees of Sec. 5's analysis), or 0 for 2; below, 2^ reads arity^ and
+ *            a block's inputs are the arity consecutive blocks
+ *            (l-1, i / arity, arity j + t), t < arity
  *  perm_x    [n]      tree position -> original point index (a permutation)
  *  xoff      [2^L+1]  space-leaf offsets into tree positions, xoff[0] = 0, xoff[2^L] = n
  *  koff      [2^L+1]  frequency-leaf offsets into columns (eigenvalue order), koff[2^L] = m
@@ -88,6 +94,7 @@ typedef enum {
 typedef struct {
   int64_t n, m;
   int32_t L;
+  int32_t arity;
   const int32_t *perm_x;
   const int64_t *xoff;
   const int64_t *koff;
@@ -213,20 +220,36 @@ bfmht_status bfmht_plan_get_tile(const bfmht_plan *plan, int32_t transpose, int3
  * counts (count >= 0 plans, all of one precision); -1 on a bad argument. */
 int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs);
 
-/* Many instances of uneven size, grouped per launch.  Instance i applies
- * plans[i] (forward when transpose == 0, else transposed) to in[i] (rows x
- * nrhs[i], ld ldin[i]) and overwrites out[i] (ld ldout[i]); instances with
- * nrhs[i] == 0 are skipped.  All plans must be uploaded and share one
- * precision.  Launch k runs the k-th stage of every instance at once (one work
+/* Mode bits of bfmht_apply_batched. */
+#define BFMHT_BATCH_TRANSPOSE 1           /* transposed applies (else forward) */
+#define BFMHT_BATCH_PERSISTENT 2          /* every stage of every instance in one launch */
+#define BFMHT_BATCH_WIDTH(w) ((w) << 8)   /* persistent tile width 16, 32 or 64 (0: 32) */
+
+/* Many instances of uneven size (the many right-hand sides and many instances
+ * of one call that the apply is used for in practice, e.g. several fields on
+ * several meshes).  Instance i applies plans[i] (forward, or transposed with
+ * BFMHT_BATCH_TRANSPOSE in mode) to in[i] (rows x nrhs[i], ld ldin[i]) and
+ * overwrites out[i] (ld ldout[i]); instances with nrhs[i] == 0 are skipped.
+ * All plans must be uploaded and share one precision.
+ * Default: launch k runs the k-th stage of every instance at once (one work
  * item per output tile of each instance), so the number of launches is the
  * largest stage count in the batch, not the sum over instances (one launch per
- * stage position and kernel shape; the per-stage segment tables travel as
- * launch arguments).  ws: device workspace, 256-byte aligned, at least
- * bfmht_batched_workspace_bytes; it holds each instance's level buffers, so
- * calls that overlap on one workspace race. */
+ * stage position and kernel shape, each instance with its plan's tile shapes;
+ * the per-stage segment tables travel as launch arguments); asynchronous.
+ * BFMHT_BATCH_PERSISTENT: one launch of resident workgroups runs every stage of
+ * every instance (64-row tiles, BFMHT_BATCH_WIDTH columns, the MFMA kernel for
+ * every RHS count); workgroups take work items in stage order from per-XCD
+ * ticket queues and wait for the instance's previous stage to finish.  This
+ * mode synchronises `stream` once at its end, to read the launch's error word,
+ * and returns EHIP if a wait gave up (bounded, seconds).  This mode is
+ * currently switched off and returns EINVAL (its GPU run did not finish in
+ * time); the per-stage launches are the batched path.
+ * ws: device workspace, 256-byte aligned, at least bfmht_batched_workspace_bytes;
+ * it holds each instance's level buffers (and the persistent launch's tables),
+ * so calls that overlap on one workspace race.  EINVAL on unknown mode bits. */
 bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
                                  const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
-                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream);
+                                 int32_t mode, void *ws, int64_t ws_bytes, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): bfmht_apply with its

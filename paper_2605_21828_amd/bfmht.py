@@ -18,7 +18,9 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbfmht.so")
+# BFMHT_LIB selects another build of the library (the AddressSanitizer build of
+# the host code, for instance); by default the in-tree libbfmht.so.
+LIB_PATH = os.environ.get("BFMHT_LIB") or os.path.join(_HERE, "libbfmht.so")
 
 F64, F32, BF16X2, BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"f64": F64, "f32": F32, "bf16x2": BF16X2, "bf16x3": BF16X3}
@@ -28,7 +30,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOSPACE", 4: "EHIP"}
 
 class bfmht_factors_host(ctypes.Structure):
     _fields_ = [
-        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("L", ctypes.c_int32),
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("L", ctypes.c_int32), ("arity", ctypes.c_int32),
         ("perm_x", ctypes.c_void_p), ("xoff", ctypes.c_void_p), ("koff", ctypes.c_void_p),
         ("rank", ctypes.c_void_p), ("ident", ctypes.c_void_p),
         ("P", ctypes.c_void_p), ("P_off", ctypes.c_void_p), ("P_len", ctypes.c_int64),
@@ -48,6 +50,12 @@ EXPORTED = [
 NOALLOC_WORKSPACE_BYTES = 256 << 20  # BFMHT_NOALLOC_WORKSPACE_BYTES
 
 PLAN_FULL_BLOCKS = 1  # plan flag: keep every ID block as the full P (no compact forward form)
+# mode bits of bfmht_apply_batched
+BATCH_TRANSPOSE, BATCH_PERSISTENT = 1, 2
+
+
+def BATCH_WIDTH(w):
+    return int(w) << 8
 
 
 def load_library(path=LIB_PATH):
@@ -132,6 +140,7 @@ def factors_struct(fs):
     )
     st = bfmht_factors_host()
     st.n, st.m, st.L = int(fs["n"]), int(fs["m"]), int(fs["L"])
+    st.arity = int(fs["arity"]) if "arity" in fs else 2
     for k in ("perm_x", "xoff", "koff", "rank", "ident", "P", "P_off", "U", "U_off"):
         setattr(st, k, keep[k].ctypes.data if keep[k].size else None)
     st.P_len, st.U_len = keep["P"].size, keep["U"].size
@@ -233,10 +242,11 @@ def bfmht_batched_workspace_bytes(plans, nrhs):
     return lib.bfmht_batched_workspace_bytes(_arr(ctypes.c_void_p, plans), len(plans), _arr(ctypes.c_int32, nrhs))
 
 
-def bfmht_apply_batched(plans, ins, ldin, outs, ldout, nrhs, transpose, ws_ptr, ws_bytes, stream=0):
+def bfmht_apply_batched(plans, ins, ldin, outs, ldout, nrhs, mode, ws_ptr, ws_bytes, stream=0):
+    """mode: BATCH_TRANSPOSE | BATCH_PERSISTENT | BATCH_WIDTH(w) bits (0 = forward, per-stage launches)."""
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     _check(lib.bfmht_apply_batched(_arr(vp, plans), len(plans), _arr(vp, ins), _arr(i64, ldin), _arr(vp, outs),
-                                   _arr(i64, ldout), _arr(i32, nrhs), int(transpose), ws_ptr, int(ws_bytes),
+                                   _arr(i64, ldout), _arr(i32, nrhs), int(mode), ws_ptr, int(ws_bytes),
                                    stream), "bfmht_apply_batched")
 
 
@@ -427,7 +437,11 @@ class Batch:
             self._ws_bytes = need
         return (self._ws.data_ptr() + 255) // 256 * 256, need
 
-    def launch(self, inputs, outputs, transpose=False):
+    def launch(self, inputs, outputs, transpose=False, persistent=False, width=0):
+        """Apply every plan to its input into its output.  persistent=True asks
+        for all stages of all instances in one launch (tile width `width`: 16,
+        32, 64, or 0 for 32); that mode is switched off in the library and
+        raises BfmhtError (EINVAL)."""
         torch = self.torch
         if len(inputs) != len(self.plans) or len(outputs) != len(self.plans):
             raise ValueError("a batch of %d plans needs %d inputs and %d outputs, got %d and %d"
@@ -441,13 +455,14 @@ class Batch:
         nrhs = [int(x.shape[1]) for x in xs]
         ws, wsb = self.workspace(nrhs)
         stream = torch.cuda.current_stream(self.device).cuda_stream
+        mode = (BATCH_TRANSPOSE if transpose else 0) | (BATCH_PERSISTENT | BATCH_WIDTH(width) if persistent else 0)
         bfmht_apply_batched([p.handle for p in self.plans], [x.data_ptr() for x in xs], [x.stride(0) for x in xs],
                             [y.data_ptr() for y in outputs], [y.stride(0) for y in outputs], nrhs,
-                            1 if transpose else 0, ws, wsb, stream)
+                            mode, ws, wsb, stream)
         return outputs
 
-    def run(self, inputs, transpose=False):
+    def run(self, inputs, transpose=False, persistent=False, width=0):
         torch = self.torch
         outs = [torch.empty(((p.m if transpose else p.n), int(x.shape[1] if x.dim() == 2 else 1)),
                             dtype=p.dtype, device=self.device) for p, x in zip(self.plans, inputs)]
-        return self.launch(inputs, outs, transpose)
+        return self.launch(inputs, outs, transpose, persistent, width)

@@ -73,11 +73,15 @@ struct Cons {
 // job's rows: entries map_off .. +K give each logical row's physical row, then
 // per consumer K entries give the g row that a skeleton row takes from that
 // consumer (-1: none).  The transposed pool at offset 0 holds a zero row.
+// With 4-ary trees a job's rows have four consumers: two jobs share the rows,
+// the second (accum = 1, launched after the first) adds its sum to them.
 struct BwdJob {
   int32_t K;
   int32_t out_row;
   int32_t nc;      // number of consumers (1 or 2)
   int32_t map_off; // -1: logical rows are physical rows, no skeleton rows
+  int32_t accum;   // 1: dst rows += this job's sum (dst first), else dst rows = the sum
+  int32_t pad;
   Cons c[2];
 };
 
@@ -90,9 +94,7 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X2 = 2, P_BF16X3 = 3 };
 
 // Everything a stage launch needs, device pointers resolved.
 struct StageArgs {
-  const void *pool;       // factor pool of this direction (BF16: hi terms)
-  const void *pool_lo;    // BF16 only: lo terms (same offsets)
-  const void *pool_lo2;   // BF16X3 only: lo2 terms
+  const void *pool;       // factor pool of this direction (FP64, or FP32 for every other precision)
   const void *jobs;       // FwdJob* or BwdJob*
   const Tile *tiles;
   int32_t ntiles;
@@ -107,8 +109,9 @@ struct StageArgs {
 };
 
 // Zero bytes after the end of every factor pool region: one reduction chunk of
-// any element type (the kernels read whole chunks past a row's end).
-constexpr int kPoolTailBytes = 128;
+// any kernel (the kernels read whole chunks past a row's end; the BF16 kernels
+// read 64 FP32 values per row and chunk).
+constexpr int kPoolTailBytes = 256;
 
 // Output rows per workgroup tile at one 16-row block per wave; tiles of twice
 // that height (two blocks per wave) are the other shape.  The plan builds tile
@@ -175,6 +178,22 @@ struct SegPack {
   Segment s[kSegsPerLaunch];
 };
 static_assert(sizeof(SegPack) <= 4096, "launch arguments are limited to 4 KB");
+
+// One segment of a persistent batched launch (device table entry; the work
+// order is built by persistent_sched.h).
+struct PSegDev {
+  StageArgs a;
+  int32_t ny;      // column tiles per tile
+  int32_t dep;     // table position whose items must all be finished first (-1: none)
+  int64_t item0;   // first per-queue ticket of this segment
+  int64_t need;    // finished items (all queues) the wait requires
+};
+// All segments in one launch of resident workgroups (64-row tiles, bn columns).
+// sync: nseg + 9 int32 words, zero at launch (counters, queue heads, error word).
+int launch_persistent(int prec, bool fwd, int bn, const PSegDev *segs, int32_t nseg, int64_t per_queue_total,
+                      int32_t *sync, int64_t spin_limit, void *stream);
+// p[0 .. n) = 0 with a kernel (no memset node when captured).
+int fill_zero_i32(int32_t *p, int64_t n, void *stream);
 
 // One launch over `items` work items of the pack's segments (item0 relative to the
 // pack); the segments share the direction and the tile shape (bn x 64 fm).

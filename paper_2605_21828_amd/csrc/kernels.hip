@@ -373,6 +373,22 @@ __device__ __forceinline__ void bwd_epilogue(const StageArgs &a, const BwdJob &J
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[fm][fn][i] += g[ci][fm][i] >= 0 ? x[fm][fn][i] : T(0);
   }
+  if (J.accum) {   // the second consumer pair of a 4-ary job: rows += this sum (clamped reads, no branch)
+    T prev[FM][FN][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          prev[fm][fn][i] = dst[(int64_t)(J.out_row + prow[fm][i]) * a.ldd + min(n0 + fn * 16 + lrow, a.nrhs - 1)];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[fm][fn][i] = prev[fm][fn][i] + acc[fm][fn][i];
+  }
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -461,10 +477,12 @@ __device__ __forceinline__ void bwd_tile(const StageArgs &a, int tix, int ny, T 
 }
 
 // ---------------------------------------------------------------------------
-// BF16 split products.  A factor value w is stored as 2 or 3 bfloat16 terms
-// (hi = bf16(w), lo = bf16(w - hi), lo2 = bf16(w - hi - lo)); right-hand-side
-// values are split the same way when a chunk is staged into LDS (once per
-// workgroup).  Products of terms whose indices sum to at most NTERM-1 are
+// BF16 split products.  A factor value w is stored in FP32 and split into 2 or
+// 3 bfloat16 terms in registers when it is loaded (hi = bf16(w), lo = bf16(w -
+// hi), lo2 = bf16(w - hi - lo), round to nearest even; each difference is exact
+// in FP32), so the factor stream costs 4 bytes per entry for either split;
+// right-hand-side values are split the same way when a chunk is staged into
+// LDS (once per workgroup).  Products of terms whose indices sum to at most NTERM-1 are
 // accumulated in FP32 by v_mfma_f32_16x16x32_bf16: hi*hi + hi*lo + lo*hi for
 // two terms, plus hi*lo2 + lo*lo + lo2*hi for three.  Only the output layout of
 // the instruction matters here: both operands use the same (lane group, element)
@@ -552,25 +570,48 @@ __device__ __forceinline__ void store_x_bf(uint16_t *Xs, const float *xr, int ti
   }
 }
 
-// This lane's KL factor values of each term for the chunk at k0 (32 bytes per
-// term).  As for load_w, values past the row's end (the next row, or the zero
-// tail of the term pool) meet zeroed right-hand-side rows, so no guard.
+// This lane's KL FP32 factor values of row `wrow` for the chunk at k0 (64
+// bytes).  As for load_w, values past the row's end (the next row, or the zero
+// tail of the pool) meet zeroed right-hand-side rows, so no guard.
 template <int NTERM, int BN>
-__device__ __forceinline__ void load_w_bf(uint4 (*wr)[2], const uint16_t *const *wrow, int k0, int lg) {
+__device__ __forceinline__ void load_w_bf(float *wr, const float *wrow, int k0, int lg) {
   typedef TilingB<NTERM, BN> Tl;
-  const int k = k0 + Tl::KL * lg;
+  copy_vec<float, Tl::KL>(wr, wrow + k0 + Tl::KL * lg);
+}
+
+// Split KL FP32 values into NTERM bf16 terms, 8 values (one MFMA operand) per
+// uint4: t[term][h] holds values 8h .. 8h+7, value 2j in the low half of word j.
+template <int NTERM>
+__device__ __forceinline__ void split_w_bf(uint4 (*t)[2], const float *w) {
 #pragma unroll
-  for (int t = 0; t < NTERM; ++t)
+  for (int h = 0; h < 2; ++h) {
+    uint32_t word[3][4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) wr[t][h] = *reinterpret_cast<const uint4 *>(wrow[t] + k + 8 * h);
+    for (int j = 0; j < 4; ++j) {
+      float r0 = w[8 * h + 2 * j], r1 = w[8 * h + 2 * j + 1];
+#pragma unroll
+      for (int u = 0; u < NTERM; ++u) {
+        word[u][j] = cvt_pk_bf16(r0, r1);
+        if (u + 1 < NTERM) {
+          r0 -= bf16_lo_f32(word[u][j]);
+          r1 -= bf16_hi_f32(word[u][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NTERM; ++u) t[u][h] = uint4{word[u][0], word[u][1], word[u][2], word[u][3]};
+  }
 }
 
 // A wave whose blocks all lie past the job's last row (`nact` = 0) issues no MFMA.
 template <int NTERM, int BN, int FM>
-__device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*wr)[NTERM][2], const uint16_t *Xs,
-                                             int lrow, int lg, int nact) {
+__device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const float (*wf)[TilingB<NTERM, BN>::KL],
+                                             const uint16_t *Xs, int lrow, int lg, int nact) {
   typedef TilingB<NTERM, BN> Tl;
   if (nact <= 0) return;
+  uint4 wr[FM][NTERM][2];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) split_w_bf<NTERM>(wr[fm], wf[fm]);
 #pragma unroll
   for (int fn = 0; fn < Tl::FN; ++fn) {
     const int off = (fn * 16 + lrow) * Tl::XS + Tl::KL * lg;
@@ -600,20 +641,20 @@ __device__ __forceinline__ void mma_chunk_bf(v4f (*acc)[BN / 16], const uint4 (*
 // holds 2 buffers per term: term t buffer j at Xs + (2 t + j) XBUF.  wrow[fm][t]:
 // term t of row fm.
 template <int NTERM, int BN, int FM, bool FULL, bool MAP, bool TWO = false>
-__device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_t *const (*wrow)[3], int nk,
+__device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const float *const *wrow, int nk,
                                               const StageArgs &a, int32_t base, const int32_t *rmap, int n0,
                                               uint16_t *Xs, int tid, int lrow, int lg, int nact,
-                                              const uint16_t *const (*wrow1)[3] = nullptr, int nk1 = 0,
+                                              const float *const *wrow1 = nullptr, int nk1 = 0,
                                               int32_t base1 = 0, int nact1 = 0) {
   typedef TilingB<NTERM, BN> Tl;
   const int nch0 = (nk + Tl::KC - 1) / Tl::KC;   // TWO: a second reduction follows in the same pipeline
   const int nchunk = nch0 + (TWO ? (nk1 + Tl::KC - 1) / Tl::KC : 0);
   if (nchunk <= 0) return;
-  uint4 wA[FM][NTERM][2], wB[FM][NTERM][2];
+  float wA[FM][Tl::KL], wB[FM][Tl::KL];
   float xB[Tl::XR];
   const int kx = 2 * (tid % 32);
   int mrow[2] = {MAP ? rmap[min(kx, nk - 1)] : 0, MAP ? rmap[min(kx + 1, nk - 1)] : 0};
-  auto load_chunk = [&](uint4 (*w)[NTERM][2], int c) {  // same order as in gemm_block
+  auto load_chunk = [&](float (*w)[Tl::KL], int c) {  // same order as in gemm_block
     const bool sec = TWO && c >= nch0;
     const int cl = sec ? c - nch0 : c;
     load_x_bf<NTERM, BN, FULL, MAP>(xB, a, sec ? base1 : base, sec ? nk1 : nk, cl * Tl::KC, n0, tid, mrow);
@@ -650,10 +691,7 @@ __device__ __forceinline__ void gemm_block_bf(v4f (*acc)[BN / 16], const uint16_
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t) {
-        wA[fm][t][0] = wB[fm][t][0];
-        wA[fm][t][1] = wB[fm][t][1];
-      }
+      for (int v = 0; v < Tl::KL; ++v) wA[fm][v] = wB[fm][v];
   }
   mma_chunk_bf<NTERM, BN, FM>(acc, wA, two ? X1 : X0, lrow, lg, na_of(two ? c + 1 : c));
   __syncthreads();
@@ -674,14 +712,10 @@ __device__ __forceinline__ void fwd_tile_bf(const StageArgs &a, int tix, int ny,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lrow = lane & 15, lg = lane >> 4;
   const int rbase = tile.m0 + wave * 16 * FM;
   const int nact = active_blocks<FM>(J.M - rbase);
-  const uint16_t *wrow[FM][3];
+  const float *wrow[FM];
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm) {
-    const int64_t roff = J.w_off + (int64_t)min(rbase + fm * 16 + lrow, J.M - 1) * J.ldw;
-    wrow[fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
-    wrow[fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
-    wrow[fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
-  }
+  for (int fm = 0; fm < FM; ++fm)
+    wrow[fm] = static_cast<const float *>(a.pool) + J.w_off + (int64_t)min(rbase + fm * 16 + lrow, J.M - 1) * J.ldw;
   v4f acc[FM][Tl::FN];
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm)
@@ -708,7 +742,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int i = 0; i < Tl::FN; ++i) acc[fm][i] = v4f{0, 0, 0, 0};
-  const uint16_t *wrow[2][FM][3];   // both consumers in one pipeline, as in bwd_tile
+  const float *wrow[2][FM];   // both consumers in one pipeline, as in bwd_tile
   int nk[2], na[2];
   int32_t gb[2];
 #pragma unroll
@@ -722,9 +756,7 @@ __device__ __forceinline__ void bwd_tile_bf(const StageArgs &a, int tix, int ny,
     for (int fm = 0; fm < FM; ++fm) {
       const int r = rbase + fm * 16 + lrow;
       const int64_t roff = on && r >= C.lo && r < C.hi ? C.wt_off + (int64_t)(r - C.lo) * C.ldwt : 0;
-      wrow[ci][fm][0] = static_cast<const uint16_t *>(a.pool) + roff;
-      wrow[ci][fm][1] = static_cast<const uint16_t *>(a.pool_lo) + roff;
-      wrow[ci][fm][2] = NTERM == 3 ? static_cast<const uint16_t *>(a.pool_lo2) + roff : nullptr;
+      wrow[ci][fm] = static_cast<const float *>(a.pool) + roff;
     }
   }
   gemm_block_bf<NTERM, BN, FM, FULL, false, true>(acc, wrow[0], nk[0], a, gb[0], nullptr, n0, Xs, tid, lrow, lg,
@@ -1056,6 +1088,13 @@ __device__ __forceinline__ void gemv_bwd_tile(const StageArgs &a, int tix, T *Xs
 #pragma unroll
     for (int it = 0; it < 4; ++it) v[it] += g[ci][it] >= 0 ? x[it] : T(0);
   }
+  if (J.accum) {   // second consumer pair of a 4-ary job: rows += this sum
+    T prev[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) prev[it] = dst[(int64_t)(J.out_row + prow[it]) * a.ldd + j];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) v[it] = prev[it] + v[it];
+  }
 #pragma unroll
   for (int it = 0; it < 4; ++it)
     if (gr[it] < J.K && kl < a.nrhs) dst[(int64_t)(J.out_row + prow[it]) * a.ldd + kl] = v[it];
@@ -1291,6 +1330,133 @@ int launch_batched_stage(int prec, bool fwd, int bn, int fm, const SegPack &pack
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched apply: every stage of every instance in one launch.  The
+// work order (persistent_sched.h) lists segments stage-major in kQueues ticket
+// queues, one per XCD bin of the tile lists; workgroup b serves queue b % 8.
+// A workgroup takes a ticket (device-scope atomic) only after finishing its
+// previous item, waits until its instance's previous stage has finished every
+// item (a per-segment count), runs the tile and counts it.  The 8 XCDs have
+// separate L2 caches: a finished tile's stores are written back with an
+// agent-scope release fence by every thread before the count is raised (a
+// release at agent scope), and the waiting side reads the count with an
+// agent-scope acquire and fences again (acquire) before loading the level
+// vector.  Every wait is bounded: past spin_limit polls the workgroup sets the
+// error word and leaves; every workgroup leaves once the word is set, so the
+// launch always ends.  sync: counters[nseg], heads[kQueues], err (int32).
+
+constexpr int kPQueues = 8;
+
+template <int P, bool FWD, int BN>
+__global__ __launch_bounds__(kNT) void persistent_kernel(const PSegDev *segs, int32_t nseg, int64_t per_queue_total,
+                                                         int32_t *sync, int64_t spin_limit) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LdsBytes<P, BN>::bytes];
+  __shared__ int64_t s_ticket;
+  __shared__ int32_t s_ok;
+  int32_t *counters = sync, *heads = sync + nseg, *err = sync + nseg + kPQueues;
+  const int x = blockIdx.x % kPQueues;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int64_t t = per_queue_total;   // leave when the error word is set
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        t = __hip_atomic_fetch_add(heads + x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ticket = t;
+    }
+    __syncthreads();
+    const int64_t t = s_ticket;
+    if (t >= per_queue_total) break;
+    int32_t lo = 0, hi = nseg - 1;   // last segment whose first ticket is <= t
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (segs[mid].item0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const PSegDev S = segs[lo];
+    if (threadIdx.x == 0) {
+      int32_t ok = 1;
+      if (S.dep >= 0) {
+        int64_t spins = 0;
+        while (__hip_atomic_load(counters + S.dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < S.need) {
+          if (++spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int64_t u = t - S.item0;
+    const int tix = (int)(u / S.ny) * kPQueues + x, col = (int)(u % S.ny);
+    if (S.a.vec && S.a.nrhs % BN == 0) run_tile<P, FWD, BN, 1, true>(S.a, tix, col, lds);
+    else run_tile<P, FWD, BN, 1, false>(S.a, tix, col, lds);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(counters + lo, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void fill_zero_kernel(int32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) p[i] = 0;
+}
+
+int fill_zero_i32(int32_t *p, int64_t n, void *stream) {
+  if (n <= 0) return 0;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + kNT - 1) / kNT, 1024);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(kNT), 0, (hipStream_t)stream, p, n);
+  return (int)hipGetLastError();
+}
+
+namespace {
+template <int P, bool FWD, int BN>
+int launch_persistent_t(const PSegDev *segs, int32_t nseg, int64_t per_queue_total, int32_t *sync,
+                        int64_t spin_limit, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<P, FWD, BN>, kNT, 0);
+  if (e != hipSuccess) return (int)e;
+  // resident workgroups, a whole number per queue, no more than the tickets need
+  int64_t grid = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+  grid = std::min<int64_t>(grid, per_queue_total * kPQueues);
+  grid = std::max<int64_t>(grid / kPQueues * kPQueues, kPQueues);
+  hipLaunchKernelGGL((persistent_kernel<P, FWD, BN>), dim3((unsigned)grid), dim3(kNT), 0, s, segs, nseg,
+                     per_queue_total, sync, spin_limit);
+  return (int)hipGetLastError();
+}
+template <int P, bool FWD>
+int launch_persistent_bn(int bn, const PSegDev *segs, int32_t nseg, int64_t pq, int32_t *sync, int64_t lim,
+                         hipStream_t s) {
+  if (bn == 16) return launch_persistent_t<P, FWD, 16>(segs, nseg, pq, sync, lim, s);
+  if (bn == 32) return launch_persistent_t<P, FWD, 32>(segs, nseg, pq, sync, lim, s);
+  return launch_persistent_t<P, FWD, 64>(segs, nseg, pq, sync, lim, s);
+}
+template <int P>
+int launch_persistent_p(bool fwd, int bn, const PSegDev *segs, int32_t nseg, int64_t pq, int32_t *sync,
+                        int64_t lim, hipStream_t s) {
+  return fwd ? launch_persistent_bn<P, true>(bn, segs, nseg, pq, sync, lim, s)
+             : launch_persistent_bn<P, false>(bn, segs, nseg, pq, sync, lim, s);
+}
+}  // namespace
+
+int launch_persistent(int prec, bool fwd, int bn, const PSegDev *segs, int32_t nseg, int64_t per_queue_total,
+                      int32_t *sync, int64_t spin_limit, void *stream) {
+  if (per_queue_total == 0 || nseg == 0) return 0;
+  if (bn != 16 && bn != 32 && bn != 64) return (int)hipErrorInvalidValue;
+  hipStream_t s = (hipStream_t)stream;
+  switch (prec) {
+    case P_F64: return launch_persistent_p<P_F64>(fwd, bn, segs, nseg, per_queue_total, sync, spin_limit, s);
+    case P_F32: return launch_persistent_p<P_F32>(fwd, bn, segs, nseg, per_queue_total, sync, spin_limit, s);
+    case P_BF16X2: return launch_persistent_p<P_BF16X2>(fwd, bn, segs, nseg, per_queue_total, sync, spin_limit, s);
+    case P_BF16X3: return launch_persistent_p<P_BF16X3>(fwd, bn, segs, nseg, per_queue_total, sync, spin_limit, s);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bfmht

@@ -18,6 +18,7 @@
 
 #include "../../include/bfmht.h"
 #include "bfmht_internal.h"
+#include "persistent_sched.h"
 
 using namespace bfmht;
 
@@ -31,30 +32,25 @@ bfmht_status fail(bfmht_status s, const std::string &msg) {
 }
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
 int32_t ldw_of(int64_t k) { return (int32_t)align_up(k, 8); }
-
-uint16_t f32_to_bf16(float x) {
-  uint32_t u;
-  std::memcpy(&u, &x, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  const uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;  // round to nearest, ties to even
-  return (uint16_t)(u >> 16);
-}
-float bf16_to_f32(uint16_t h) {
-  const uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
 
 struct StageDesc {
   int kind;   // 0: level 0 (reads c), 1: transfer level, 2: final (writes f through perm_x)
   int level;
   bool skip = false;    // forward only: an all-identity level folded into the first later stage
   bool edge = false;    // forward only: the first stage after the folded levels (reads c)
-  int64_t fjob0, nfjob, bjob0, nbjob;
-  int64_t ftile0[2], nftile[2], btile0[2], nbtile[2];  // tile lists for 64- and 128-row tiles
+  int64_t fjob0, nfjob;
+  int64_t ftile0[2], nftile[2];   // tile lists for 64- and 128-row tiles
+  // transposed jobs in up to two parts launched in turn: with 4-ary trees a
+  // job has four consumers, two in part 0 (which writes its rows) and two in
+  // part 1 (which adds to them); binary trees have part 0 only
+  int64_t bjob0[2], nbjob[2];
+  int64_t btile0[2][2], nbtile[2][2];   // [part][height]
 };
 
 }  // namespace
@@ -63,10 +59,11 @@ struct bfmht_plan {
   int prec = 0;
   int64_t n = 0, m = 0;
   int L = 0;
+  int arity = 2;         // children per tree node (2 or 4)
+  int extra_parts = 0;   // transposed stages with a second job part (4-ary trees)
   int32_t max_nrhs = 1;
   int64_t esz = 0;       // bytes per element of level buffers and I/O
-  int64_t wsz = 0;       // bytes per element of the factor pool (per term for BF16)
-  int nterms = 1;        // 1, or 2 / 3 BF16 terms
+  int64_t wsz = 0;       // bytes per element of the factor pool (FP64, else FP32; BF16 terms are split on load)
   std::vector<StageDesc> stages;
   std::vector<int64_t> level_rows;
   int64_t max_rows = 0;
@@ -80,8 +77,8 @@ struct bfmht_plan {
   int64_t fold_copies = 0;         // copies of each row of c at level nfold-1
   std::vector<int32_t> fold_inv;   // per row of c, its level nfold-1 rows in space-node order
   int64_t off_fold = 0;
-  int64_t off_pool[3] = {0, 0, 0};   // forward pool, one region per term
-  int64_t off_tpool[3] = {0, 0, 0};  // transposed pool
+  int64_t off_pool = 0;    // forward pool
+  int64_t off_tpool = 0;   // transposed pool
   int64_t off_fjobs = 0, off_bjobs = 0, off_tiles = 0, off_perm = 0, dev_bytes = 0;
   std::vector<unsigned char> staging;
   char *dev = nullptr;
@@ -96,8 +93,10 @@ bfmht_status validate(const bfmht_factors_host *f) {
   if (!f) return fail(BFMHT_EINVAL, "factors is NULL");
   if (f->n < 0 || f->m < 0) return fail(BFMHT_EINVAL, "negative n or m");
   if (f->n >= (1ll << 31) || f->m >= (1ll << 31)) return fail(BFMHT_EINVAL, "n or m exceeds 2^31-1");
-  if (f->L < 0 || f->L > 24) return fail(BFMHT_EINVAL, "L out of range [0, 24]");
-  const int64_t nb = 1ll << f->L;
+  const int a = f->arity == 0 ? 2 : f->arity;
+  if (a != 2 && a != 4) return fail(BFMHT_EINVAL, "arity must be 2 or 4 (0 means 2)");
+  if (f->L < 0 || f->L * (a == 4 ? 2 : 1) > 24) return fail(BFMHT_EINVAL, "L out of range (arity^L above 2^24)");
+  const int64_t nb = 1ll << (f->L * (a == 4 ? 2 : 1));
   if (!f->xoff || !f->koff || !f->rank || !f->ident || !f->P_off || !f->U_off || (f->n > 0 && !f->perm_x))
     return fail(BFMHT_EINVAL, "a required factor array is NULL");
   if (f->xoff[0] != 0 || f->xoff[nb] != f->n) return fail(BFMHT_EINVAL, "xoff must run from 0 to n");
@@ -113,16 +112,16 @@ bfmht_status validate(const bfmht_factors_host *f) {
     seen[p] = 1;
   }
   for (int lvl = 0; lvl <= f->L; ++lvl) {
-    const int64_t nf = 1ll << (f->L - lvl);
+    const int64_t nf = ipow(a, f->L - lvl);
     for (int64_t q = 0; q < nb; ++q) {
       const int64_t r = f->rank[lvl * nb + q];
-      int64_t rin;
+      int64_t rin = 0;
       if (lvl == 0) {
         rin = f->koff[q + 1] - f->koff[q];
       } else {
-        const int64_t i = q / nf, j = q % nf, p = i >> 1;
-        const int64_t q1 = p * 2 * nf + 2 * j;
-        rin = (int64_t)f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1];
+        const int64_t i = q / nf, j = q % nf, p = i / a;
+        const int64_t q1 = p * a * nf + a * j;   // first of the block's a inputs
+        for (int t = 0; t < a; ++t) rin += f->rank[(lvl - 1) * nb + q1 + t];
       }
       if (r < 0 || r > rin)
         return fail(BFMHT_EINVAL, "rank out of range at level " + std::to_string(lvl) + " block " + std::to_string(q));
@@ -200,12 +199,13 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   p->n = f->n;
   p->m = f->m;
   p->L = f->L;
+  p->arity = f->arity == 0 ? 2 : f->arity;
   p->max_nrhs = max_nrhs;
   p->esz = prec == BFMHT_F64 ? 8 : 4;
-  p->wsz = prec == BFMHT_F64 ? 8 : (prec == BFMHT_F32 ? 4 : 2);
-  p->nterms = prec == BFMHT_BF16X2 ? 2 : (prec == BFMHT_BF16X3 ? 3 : 1);
+  p->wsz = prec == BFMHT_F64 ? 8 : 4;
   const int L = f->L;
-  const int64_t nb = 1ll << L;
+  const int A = p->arity;
+  const int64_t nb = ipow(A, L);
 
   // Row offsets of every block inside its level buffer (space-major order).
   std::vector<std::vector<int64_t>> off(L + 1, std::vector<int64_t>(nb + 1, 0));
@@ -234,10 +234,17 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   std::vector<Src> blocks;
   std::vector<int64_t> woff_P((size_t)(L + 1) * nb, -1), woff_U(nb, -1);
   int64_t pool = 0;
+  // first of the A inputs of block q at level lvl (they are consecutive blocks of level lvl-1)
+  auto child0 = [&](int lvl, int64_t q) -> int64_t {
+    const int64_t nf = ipow(A, L - lvl), i = q / nf, j = q % nf;
+    return (i / A) * A * nf + A * j;
+  };
   auto rin_of = [&](int lvl, int64_t q) -> int64_t {
     if (lvl == 0) return f->koff[q + 1] - f->koff[q];
-    const int64_t nf = 1ll << (L - lvl), i = q / nf, j = q % nf, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
-    return (int64_t)f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1];
+    const int64_t q1 = child0(lvl, q);
+    int64_t r = 0;
+    for (int t = 0; t < A; ++t) r += f->rank[(lvl - 1) * nb + q1 + t];
+    return r;
   };
   std::vector<int64_t> bidx_P((size_t)(L + 1) * nb, -1);
   for (int lvl = 0; lvl <= L; ++lvl)
@@ -408,16 +415,18 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
     }
   };
   auto add_btiles = [&](StageDesc &s) {
-    std::vector<std::pair<int64_t, int64_t>> jc;
-    for (int64_t t = s.bjob0; t < s.bjob0 + s.nbjob; ++t) {
-      int64_t cost = 1;   // reduction length per tile row, averaged over the job's rows
-      for (int c = 0; c < bj[t].nc; ++c)
-        cost += (int64_t)bj[t].c[c].M * (bj[t].c[c].hi - bj[t].c[c].lo) / std::max<int32_t>(bj[t].K, 1);
-      jc.push_back({cost, bj[t].K});
-    }
-    for (int h = 0; h < 2; ++h) {
-      s.btile0[h] = (int64_t)tiles.size();
-      s.nbtile[h] = order(jc, kTileRows << h);
+    for (int part = 0; part < 2; ++part) {
+      std::vector<std::pair<int64_t, int64_t>> jc;
+      for (int64_t t = s.bjob0[part]; t < s.bjob0[part] + s.nbjob[part]; ++t) {
+        int64_t cost = 1;   // reduction length per tile row, averaged over the job's rows
+        for (int c = 0; c < bj[t].nc; ++c)
+          cost += (int64_t)bj[t].c[c].M * (bj[t].c[c].hi - bj[t].c[c].lo) / std::max<int32_t>(bj[t].K, 1);
+        jc.push_back({cost, bj[t].K});
+      }
+      for (int h = 0; h < 2; ++h) {
+        s.btile0[part][h] = (int64_t)tiles.size();
+        s.nbtile[part][h] = order(jc, kTileRows << h);
+      }
     }
   };
   auto cons_of = [&](int lvl, int64_t q) -> ConsIn {
@@ -428,7 +437,9 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
     s.kind = lvl == 0 ? 0 : (lvl <= L ? 1 : 2);
     s.level = lvl;
     s.fjob0 = (int64_t)fj.size();
-    s.bjob0 = (int64_t)bj.size();
+    s.bjob0[0] = (int64_t)bj.size();
+    s.bjob0[1] = 0;
+    s.nbjob[1] = 0;
     if (lvl == 0) {
       for (int64_t j = 0; j < nb; ++j) {
         const bool id = f->ident[j] != 0;
@@ -438,22 +449,33 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
         bj.push_back(bjob((int32_t)k, (int32_t)f->koff[j], 1, &c0));
       }
     } else if (lvl <= L) {
-      const int64_t nf = 1ll << (L - lvl);
-      for (int64_t i = 0; i < (1ll << lvl); ++i)
+      const int64_t nf = ipow(A, L - lvl);
+      for (int64_t i = 0; i < ipow(A, lvl); ++i)
         for (int64_t j = 0; j < nf; ++j) {
-          const int64_t q = i * nf + j, pp = i >> 1, q1 = pp * 2 * nf + 2 * j;
+          const int64_t q = i * nf + j, q1 = child0(lvl, q);
           const bool id = f->ident[lvl * nb + q] != 0;
           const int64_t k = rin_of(lvl, q);
           fj.push_back(fjob(id ? -1 : woff_P[lvl * nb + q], bidx_P[lvl * nb + q], f->rank[lvl * nb + q], k,
                             off[lvl - 1][q1], off[lvl][q]));
         }
-      for (int64_t pp = 0; pp < (1ll << (lvl - 1)); ++pp)
-        for (int64_t j = 0; j < nf; ++j) {
-          const int64_t q1 = pp * 2 * nf + 2 * j;
-          const ConsIn cs[2] = {cons_of(lvl, (2 * pp) * nf + j), cons_of(lvl, (2 * pp + 1) * nf + j)};
-          bj.push_back(bjob((int32_t)(f->rank[(lvl - 1) * nb + q1] + f->rank[(lvl - 1) * nb + q1 + 1]),
-                            (int32_t)off[lvl - 1][q1], 2, cs));
-        }
+      // a transposed job owns the A consecutive input blocks of one parent pp
+      // and frequency node j, and sums the products of their A consumers (the
+      // blocks (A pp + s, j)); consumers 2 and 3 of a 4-ary job go to part 1
+      for (int part = 0; part < A / 2; ++part) {
+        s.bjob0[part] = (int64_t)bj.size();
+        for (int64_t pp = 0; pp < ipow(A, lvl - 1); ++pp)
+          for (int64_t j = 0; j < nf; ++j) {
+            const int64_t q1 = pp * A * nf + A * j;
+            int64_t K = 0;
+            for (int t = 0; t < A; ++t) K += f->rank[(lvl - 1) * nb + q1 + t];
+            const ConsIn cs[2] = {cons_of(lvl, (A * pp + 2 * part) * nf + j),
+                                  cons_of(lvl, (A * pp + 2 * part + 1) * nf + j)};
+            BwdJob J = bjob((int32_t)K, (int32_t)off[lvl - 1][q1], 2, cs);
+            J.accum = part;
+            bj.push_back(J);
+          }
+        s.nbjob[part] = (int64_t)bj.size() - s.bjob0[part];
+      }
     } else {
       for (int64_t i = 0; i < nb; ++i) {
         const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
@@ -463,7 +485,7 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       }
     }
     s.nfjob = (int64_t)fj.size() - s.fjob0;
-    s.nbjob = (int64_t)bj.size() - s.bjob0;
+    if (s.kind != 1) s.nbjob[0] = (int64_t)bj.size() - s.bjob0[0];
     p->stages.push_back(s);
   }
   p->tpool_elems = tpool;
@@ -490,9 +512,8 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       for (int64_t t = 0; t < f->rank[j]; ++t) pi[off[0][j] + t] = f->koff[j] + t;
     for (int lvl = 1; lvl < nfold; ++lvl) {
       std::vector<int64_t> nx((size_t)off[lvl][nb]);
-      const int64_t nf = 1ll << (L - lvl);
       for (int64_t q = 0; q < nb; ++q) {
-        const int64_t i = q / nf, j = q % nf, q1 = (i >> 1) * 2 * nf + 2 * j;
+        const int64_t q1 = child0(lvl, q);   // an identity block's rows are its inputs' rows, in order
         for (int64_t t = 0; t < f->rank[lvl * nb + q]; ++t) nx[off[lvl][q] + t] = pi[off[lvl - 1][q1] + t];
       }
       pi.swap(nx);
@@ -500,11 +521,12 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
     for (int k = 0; k < nfold; ++k) p->stages[k].skip = true;
     p->fwd_edge = nfold;
     // Transposed direction: the folded levels sum the copies of each row of c,
-    // pairwise over the space nodes (a balanced tree).  One gather-sum over the
-    // level nfold-1 rows replaces those stages in a single apply.  The gather-sum
-    // kernel takes at most 2^15 copies; deeper runs of identity levels keep their
-    // transposed stages (then nfold stays 0).
-    const int64_t C = 1ll << (nfold - 1), rows = off[nfold - 1][nb];
+    // pairwise over the space nodes (a balanced tree; a 4-ary level adds its
+    // four copies as (c0 + c1) + (c2 + c3), the same tree).  One gather-sum over
+    // the level nfold-1 rows replaces those stages in a single apply.  The
+    // gather-sum kernel takes at most 2^15 copies; deeper runs of identity
+    // levels keep their transposed stages (then nfold stays 0).
+    const int64_t C = ipow(A, nfold - 1), rows = off[nfold - 1][nb];
     if (C <= kFoldMaxCopies && rows == f->m * C) {
       std::vector<int32_t> cnt((size_t)f->m, 0);
       p->fold_inv.assign((size_t)rows, -1);
@@ -542,6 +564,7 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   for (auto &s : p->stages) {
     add_ftiles(s);
     add_btiles(s);
+    if (s.nbjob[1] > 0) ++p->extra_parts;
   }
   for (int d = 0; d < 2; ++d) {
     p->rows[d].assign(p->stages.size(), kTileRows);
@@ -555,14 +578,10 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   // reduction chunk (128 bytes for every element type): the kernels read whole
   // chunks past a row's end without a guard.
   int64_t cur = 0;
-  for (int t = 0; t < p->nterms; ++t) {
-    p->off_pool[t] = cur;
-    cur = align_up(cur + pool * p->wsz + kPoolTailBytes, 256);
-  }
-  for (int t = 0; t < p->nterms; ++t) {
-    p->off_tpool[t] = cur;
-    cur = align_up(cur + tpool * p->wsz + kPoolTailBytes, 256);
-  }
+  p->off_pool = cur;
+  cur = align_up(cur + pool * p->wsz + kPoolTailBytes, 256);
+  p->off_tpool = cur;
+  cur = align_up(cur + tpool * p->wsz + kPoolTailBytes, 256);
   p->off_fjobs = cur;
   cur = align_up(cur + (int64_t)fj.size() * (int64_t)sizeof(FwdJob), 256);
   p->off_bjobs = cur;
@@ -579,20 +598,11 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
 
   p->staging.assign((size_t)p->dev_bytes, 0);
   unsigned char *S = p->staging.data();
-  auto put = [&](const int64_t *base, int64_t e, double x) {
-    if (prec == BFMHT_F64) {
-      reinterpret_cast<double *>(S + base[0])[e] = x;
-    } else if (prec == BFMHT_F32) {
-      reinterpret_cast<float *>(S + base[0])[e] = (float)x;
-    } else {
-      const float x32 = (float)x;
-      const uint16_t hi = f32_to_bf16(x32);
-      const float r1 = x32 - bf16_to_f32(hi);
-      const uint16_t lo = f32_to_bf16(r1);
-      reinterpret_cast<uint16_t *>(S + base[0])[e] = hi;
-      reinterpret_cast<uint16_t *>(S + base[1])[e] = lo;
-      if (p->nterms == 3) reinterpret_cast<uint16_t *>(S + base[2])[e] = f32_to_bf16(r1 - bf16_to_f32(lo));
-    }
+  // FP64 pools for the plain path, FP32 otherwise (the BF16 kernels split each
+  // FP32 value into its bf16 terms when they load it)
+  auto put = [&](int64_t base, int64_t e, double x) {
+    if (prec == BFMHT_F64) reinterpret_cast<double *>(S + base)[e] = x;
+    else reinterpret_cast<float *>(S + base)[e] = (float)x;
   };
   int64_t bo = 0;
   for (const Src &b : blocks) {
@@ -696,20 +706,18 @@ int32_t vec_ok(const void *src, int64_t ld, int64_t esz) {
   return (((uintptr_t)src) % 16 == 0 && (ld * esz) % 16 == 0) ? 1 : 0;
 }
 
-StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h) {
+// part: the transposed stage's job part (0, or 1 for the second consumer pair of 4-ary trees)
+StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h, int part) {
   StageArgs a{};
-  const int64_t *po = fwd ? p->off_pool : p->off_tpool;
-  a.pool = p->dev + po[0];
-  a.pool_lo = p->nterms > 1 ? p->dev + po[1] : nullptr;
-  a.pool_lo2 = p->nterms > 2 ? p->dev + po[2] : nullptr;
+  a.pool = p->dev + (fwd ? p->off_pool : p->off_tpool);
   if (fwd) {
     a.jobs = p->dev + p->off_fjobs + s.fjob0 * (int64_t)sizeof(FwdJob);
     a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.ftile0[h];
     a.ntiles = (int32_t)s.nftile[h];
   } else {
-    a.jobs = p->dev + p->off_bjobs + s.bjob0 * (int64_t)sizeof(BwdJob);
-    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0[h];
-    a.ntiles = (int32_t)s.nbtile[h];
+    a.jobs = p->dev + p->off_bjobs + s.bjob0[part] * (int64_t)sizeof(BwdJob);
+    a.tiles = reinterpret_cast<const Tile *>(p->dev + p->off_tiles) + s.btile0[part][h];
+    a.ntiles = (int32_t)s.nbtile[part][h];
   }
   // the forward leaf stage scatters its rows to the points' order
   a.rowmap = fwd && s.kind == 2 ? reinterpret_cast<const int32_t *>(p->dev + p->off_perm) : nullptr;
@@ -720,8 +728,8 @@ StageArgs base_args(const bfmht_plan *p, const StageDesc &s, bool fwd, int h) {
 // Arguments of stage s of one apply of plan p (forward or transposed) between
 // user buffers in/out and the two level buffers buf[0], buf[1].
 StageArgs stage_io(const bfmht_plan *p, const StageDesc &s, bool fwd, int rows, const void *in, int64_t ldin,
-                   void *out, int64_t ldout, int32_t nrhs, char *const buf[2]) {
-  StageArgs a = base_args(p, s, fwd, rows == 2 * kTileRows ? 1 : 0);
+                   void *out, int64_t ldout, int32_t nrhs, char *const buf[2], int part = 0) {
+  StageArgs a = base_args(p, s, fwd, rows == 2 * kTileRows ? 1 : 0, part);
   a.nrhs = nrhs;
   if (fwd) {
     // stage l reads level l-1 (or c) and writes level l (or f)
@@ -771,16 +779,22 @@ bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ld
     const StageDesc &s = p->stages[si];
     if (fwd ? s.skip : si < p->nfold) continue;   // folded identity levels
     const int d = fwd ? 0 : 1;
-    if (gemv) {   // few right-hand sides: vector FMAs over the 64-row tiles
-      StageArgs a = stage_io(p, s, fwd, kTileRows, in, ldin, out, ldout, nrhs, buf);
-      const int e = launch_gemv_stage(p->prec, fwd, a, stream);
+    // a transposed 4-ary stage runs its second consumer pair as a second launch
+    // that adds to the rows the first one wrote
+    const int parts = fwd || s.nbjob[1] == 0 ? 1 : 2;
+    for (int part = 0; part < parts; ++part) {
+      if (gemv) {   // few right-hand sides: vector FMAs over the 64-row tiles
+        StageArgs a = stage_io(p, s, fwd, kTileRows, in, ldin, out, ldout, nrhs, buf, part);
+        const int e = launch_gemv_stage(p->prec, fwd, a, stream);
+        if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
+        continue;
+      }
+      const int rows = p->rows[d][si], cols = pick_cols(p->cols[d][si], nrhs);
+      StageArgs a = stage_io(p, s, fwd, rows, in, ldin, out, ldout, nrhs, buf, part);
+      const int e =
+          fwd ? launch_fwd_stage(p->prec, a, rows, cols, stream) : launch_bwd_stage(p->prec, a, rows, cols, stream);
       if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
-      continue;
     }
-    const int rows = p->rows[d][si], cols = pick_cols(p->cols[d][si], nrhs);
-    StageArgs a = stage_io(p, s, fwd, rows, in, ldin, out, ldout, nrhs, buf);
-    const int e = fwd ? launch_fwd_stage(p->prec, a, rows, cols, stream) : launch_bwd_stage(p->prec, a, rows, cols, stream);
-    if (e) return fail(BFMHT_EHIP, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
   }
   if (!fwd && p->nfold > 0) {   // sum the copies of each row of c (the folded transposed levels)
     const int e = launch_fold_sum((int)p->esz, buf[(p->nfold - 1) & 1], nrhs,
@@ -953,7 +967,23 @@ struct BatchLayout {
   int64_t total = 0;
   int32_t nseg = 0;
   std::vector<int64_t> buf_off;  // per instance
+  int64_t table_off = 0;         // persistent launch: segment table, then its sync words
+  int64_t sync_off = 0;
 };
+
+// Polls of a persistent workgroup's wait before it gives up (each poll is one
+// device-scope load and a short sleep, about a microsecond): a few seconds, far
+// above any stage's duration.
+constexpr int64_t kPersistentSpinLimit = 1ll << 22;
+
+// The persistent launch is switched off: its one GPU run (every stage of a
+// 7-instance batch, FP64) did not finish within minutes although every wait
+// is bounded (no fault).  The likely cause, read from the code: each poll of a
+// waiting workgroup is an agent-scope acquire, which invalidates its XCD's L2,
+// and every finished tile writes the whole L2 back, so thousands of resident
+// workgroups thrash the caches the working ones read from.  Until a version
+// that polls without invalidating has run, the mode returns EINVAL.
+constexpr bool kPersistentLaunch = false;
 
 bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const int32_t *nrhs, BatchLayout &L) {
   if (count < 0) return fail(BFMHT_EINVAL, "count < 0");
@@ -964,20 +994,98 @@ bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const i
     if (!plans[i]) return fail(BFMHT_EINVAL, "NULL plan in batch");
     if (nrhs[i] < 0) return fail(BFMHT_EINVAL, "nrhs < 0 in batch");
     if (plans[i]->prec != plans[0]->prec) return fail(BFMHT_EINVAL, "plans of a batch must share one precision");
-    if (nrhs[i] > 0) L.nseg += (int32_t)plans[i]->stages.size();
+    if (nrhs[i] > 0) L.nseg += (int32_t)plans[i]->stages.size() + plans[i]->extra_parts;
   }
   int64_t cur = 0;
   for (int32_t i = 0; i < count; ++i) {
     L.buf_off[i] = cur;
     if (nrhs[i] > 0) cur += 2 * level_buffer_bytes(plans[i], nrhs[i]);
   }
-  L.total = std::max<int64_t>(cur, 256);
+  // the persistent launch's segment table and sync words (at most one segment per stage)
+  L.table_off = align_up(cur, 256);
+  L.sync_off = align_up(L.table_off + (int64_t)L.nseg * (int64_t)sizeof(PSegDev), 256);
+  cur = L.sync_off + ((int64_t)L.nseg + kQueues + 1) * 4;
+  L.total = std::max<int64_t>(align_up(cur, 256), 256);
+  return BFMHT_OK;
+}
+
+// Every stage of every instance in one persistent launch (64-row tiles of bn
+// columns, MFMA kernel for every instance).  Synchronises the stream once to
+// read the launch's error word.
+bfmht_status apply_persistent(const bfmht_plan *const *plans, int32_t count, const void *const *in,
+                              const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                              bool fwd, int bn, const BatchLayout &L, char *ws, void *stream) {
+  std::vector<PSegInfo> info;
+  std::vector<PSegDev> segs;
+  for (int32_t i = 0; i < count; ++i) {
+    const bfmht_plan *p = plans[i];
+    if (nrhs[i] == 0) continue;
+    if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
+    if ((!in[i] && (fwd ? p->m : p->n) > 0) || (!out[i] && (fwd ? p->n : p->m) > 0))
+      return fail(BFMHT_EINVAL, "NULL input or output in batch");
+    if (((fwd ? p->m : p->n) > 0 && ldin[i] < nrhs[i]) || ((fwd ? p->n : p->m) > 0 && ldout[i] < nrhs[i]))
+      return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
+    char *base = ws + L.buf_off[i];
+    char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
+    if (!fwd) {
+      const int e = gather_input(p, in[i], ldin[i], nrhs[i], buf, stream);
+      if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
+    }
+    const int S = (int)p->stages.size();
+    int pos = 0;   // position in the instance's stage sequence (a 4-ary transposed stage takes two)
+    for (int k = 0; k < S; ++k) {
+      const int si = fwd ? k : S - 1 - k;
+      if (fwd && p->stages[si].skip) continue;   // folded identity level: no items
+      const int parts = fwd || p->stages[si].nbjob[1] == 0 ? 1 : 2;
+      for (int part = 0; part < parts; ++part) {
+        PSegDev d{};
+        d.a = stage_io(p, p->stages[si], fwd, kTileRows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf, part);
+        d.ny = (nrhs[i] + bn - 1) / bn;
+        info.push_back({i, pos++, (int64_t)(d.a.ntiles / kQueues) * d.ny});
+        segs.push_back(d);
+      }
+    }
+  }
+  const PSchedule sch = build_schedule(info);
+  const int32_t nseg = (int32_t)sch.seg.size();
+  if (nseg == 0) return BFMHT_OK;
+  if (sch.per_queue_total >= (1ll << 30)) return fail(BFMHT_EINVAL, "persistent launch: too many work items");
+  if (nseg > L.nseg) return fail(BFMHT_EINVAL, "persistent schedule larger than its table");
+  std::vector<PSegDev> table(nseg);
+  for (int32_t q = 0; q < nseg; ++q) {
+    table[q] = segs[sch.seg[q]];
+    table[q].item0 = sch.item0[q];
+    table[q].dep = sch.dep[q];
+    table[q].need = sch.need[q];
+  }
+  auto *dtab = reinterpret_cast<PSegDev *>(ws + L.table_off);
+  auto *sync = reinterpret_cast<int32_t *>(ws + L.sync_off);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(dtab, table.data(), table.size() * sizeof(PSegDev), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("persistent table upload: ") + hipGetErrorString(e));
+  int rc = fill_zero_i32(sync, (int64_t)nseg + kQueues + 1, stream);
+  if (!rc) rc = launch_persistent(plans[0]->prec, fwd, bn, dtab, nseg, sch.per_queue_total, sync,
+                                  kPersistentSpinLimit, stream);
+  if (rc) return fail(BFMHT_EHIP, std::string("persistent launch: ") + hipGetErrorString((hipError_t)rc));
+  int32_t err = 0;
+  e = hipMemcpyAsync(&err, sync + nseg + kQueues, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+  if (err) return fail(BFMHT_EHIP, "persistent launch: a workgroup's wait for an earlier stage timed out");
   return BFMHT_OK;
 }
 
 bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
                            const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
-                           int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
+                           int32_t mode, void *ws, int64_t ws_bytes, void *stream) {
+  if (mode & ~(BFMHT_BATCH_TRANSPOSE | BFMHT_BATCH_PERSISTENT | BFMHT_BATCH_WIDTH(0xff)))
+    return fail(BFMHT_EINVAL, "unknown batch mode bits");
+  const bool persistent = (mode & BFMHT_BATCH_PERSISTENT) != 0;
+  const int pwidth = (mode >> 8) & 0xff;
+  if (persistent && pwidth != 0 && pwidth != 16 && pwidth != 32 && pwidth != 64)
+    return fail(BFMHT_EINVAL, "persistent tile width must be 0, 16, 32 or 64");
+  if (persistent && !kPersistentLaunch)
+    return fail(BFMHT_EINVAL, "the persistent batched launch is switched off (its GPU run did not finish in time)");
   BatchLayout L;
   bfmht_status st = batch_layout(plans, count, nrhs, L);
   if (st != BFMHT_OK) return st;
@@ -985,7 +1093,9 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
   if (!in || !ldin || !out || !ldout || !ws) return fail(BFMHT_EINVAL, "NULL batch argument");
   if (((uintptr_t)ws) % 256) return fail(BFMHT_EINVAL, "workspace must be 256-byte aligned");
   if (ws_bytes < L.total) return fail(BFMHT_ENOSPACE, "workspace too small for the batch");
-  const bool fwd = transpose == 0;
+  const bool fwd = (mode & BFMHT_BATCH_TRANSPOSE) == 0;
+  if (persistent) return apply_persistent(plans, count, in, ldin, out, ldout, nrhs, fwd, pwidth ? pwidth : 32, L,
+                                          static_cast<char *>(ws), stream);
   std::vector<std::vector<Segment>> per(count);
   size_t maxS = 0;
   for (int32_t i = 0; i < count; ++i) {
@@ -1005,7 +1115,9 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
     const int S = (int)p->stages.size();
     const bool gemv = nrhs[i] <= kGemvMaxRhs && (p->prec == BFMHT_F32 || p->prec == BFMHT_F64);
     for (int k = 0; k < S; ++k) {
-      const int si = fwd ? k : S - 1 - k;
+     const int si = fwd ? k : S - 1 - k;
+     const int parts = fwd || p->stages[si].nbjob[1] == 0 ? 1 : 2;   // 4-ary transposed: two launches
+     for (int part = 0; part < parts; ++part) {
       Segment sg{};
       if (fwd && p->stages[si].skip) {   // folded identity level: an empty segment keeps the stage positions aligned
         per[i].push_back(sg);
@@ -1013,7 +1125,7 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
       }
       const int d = fwd ? 0 : 1;
       const int rows = gemv ? kTileRows : p->rows[d][si];
-      sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf);
+      sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf, part);
       sg.fwd = fwd ? 1 : 0;
       if (gemv) {   // few right-hand sides: the vector-FMA kernel, as for a single apply
         sg.fm = 0;
@@ -1026,6 +1138,7 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
       }
       sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
       per[i].push_back(sg);
+     }
     }
     maxS = std::max(maxS, per[i].size());
   }
@@ -1088,9 +1201,9 @@ int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t co
 
 bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
                                  const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
-                                 int32_t transpose, void *ws, int64_t ws_bytes, void *stream) {
+                                 int32_t mode, void *ws, int64_t ws_bytes, void *stream) {
   try {
-    return apply_batched(plans, count, in, ldin, out, ldout, nrhs, transpose, ws, ws_bytes, stream);
+    return apply_batched(plans, count, in, ldin, out, ldout, nrhs, mode, ws, ws_bytes, stream);
   } catch (...) {
     return fail(BFMHT_ENOSPACE, "host memory exhausted while grouping the batch");
   }

@@ -300,3 +300,52 @@ def test_deep_all_identity_factor_set_creates_a_plan():
         assert B.bfmht_workspace_bytes(h, 1) >= 2 * (1 << 16) * 4
     finally:
         B.bfmht_plan_destroy(h)
+
+
+def test_batched_mode_bits_are_checked_before_any_device_work(good):
+    """Unknown mode bits and the (switched-off) persistent launch are refused
+    on the host (the plans here are never uploaded)."""
+    import ctypes
+    h = B.bfmht_plan_create(good, B.F32, 4)
+    try:
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        plans = (vp * 1)(h)
+        one = (vp * 1)(None)
+        lds = (i64 * 1)(4)
+        nr = (i32 * 1)(4)
+        for mode, msg in ((4, "unknown batch mode"), (1 << 20, "unknown batch mode"),
+                          (B.BATCH_PERSISTENT, "switched off"),
+                          (B.BATCH_PERSISTENT | B.BATCH_WIDTH(48), "tile width")):
+            st = B.lib.bfmht_apply_batched(plans, 1, one, lds, one, lds, nr, mode, None, 0, None)
+            assert st == B.EINVAL, mode
+            assert msg in B.lib.bfmht_last_error().decode(), mode
+    finally:
+        B.bfmht_plan_destroy(h)
+
+
+@pytest.mark.parametrize("seed,n,m,L,p_id", [(40, 300, 200, 2, 0.0), (41, 700, 256, 3, 0.7), (42, 64, 40, 1, 0.5)])
+def test_quadtree_factor_sets_create_plans(seed, n, m, L, p_id):
+    """4-ary factor sets (arity 4): validated, laid out, and counted like the
+    binary ones; the transposed direction has a second job part per transfer level."""
+    fs = random_factor_set(seed, n, m, L, max_rank=20, p_id_form=p_id, arity=4)
+    full = fs["P"].size + fs["U"].size
+    h = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_FULL_BLOCKS)
+    try:
+        assert B.bfmht_plan_stored_entries(h, False) == full
+        assert B.bfmht_plan_num_stages(h) == L + 2
+        assert B.bfmht_workspace_bytes(h, 4) > 0
+    finally:
+        B.bfmht_plan_destroy(h)
+    h = B.bfmht_plan_create(fs, B.BF16X3, 4)
+    B.bfmht_plan_destroy(h)
+
+
+def test_arity_other_than_two_or_four_is_rejected(good):
+    bad = dict(good, arity=np.int64(3))
+    with pytest.raises(B.BfmhtError) as e:
+        B.bfmht_plan_create(bad, B.F32, 1)
+    assert e.value.status == B.EINVAL and "arity" in str(e.value)
+    # a 4-ary set whose offsets are sized for a binary tree fails the offset check
+    bad4 = dict(good, arity=np.int64(4))
+    with pytest.raises(B.BfmhtError):
+        B.bfmht_plan_create(bad4, B.F32, 1)
