@@ -108,7 +108,9 @@ typedef struct {
   int64_t U_len;
 } bfmht_factors_host;
 
-/* Validate the factor set and build the device layout for one precision.
+/* Validate the factor set (the bases, transfer blocks and leaf bases that
+ * Alg. "Butterfly factorization" of Sec. 2 returns) and build the device
+ * layout for one precision.
  * On success *plan owns host metadata (stage tables, converted factors staged
  * for upload); on failure *plan is set to NULL.  max_nrhs >= 1 records the
  * largest nrhs the caller means to use; it sizes nothing (workspace is per
@@ -130,35 +132,41 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precisio
 bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *factors, bfmht_precision prec, int32_t max_nrhs,
                                   int32_t flags, bfmht_plan **plan);
 
-/* Factor entries one apply reads: transpose = 0 for the forward direction
+/* Factor entries one apply reads (storage and apply cost coincide: every
+ * stored block is applied once per vector, Sec. 6.2): transpose = 0 for the forward direction
  * (compact blocks count T only), 1 for the transposed direction (every block
  * in full); -1 if plan is NULL. */
 int64_t bfmht_plan_stored_entries(const bfmht_plan *plan, int32_t transpose);
 
-/* Bytes of device memory the plan needs for its factors and tables. */
+/* Bytes of device memory the plan needs for its factors (the Sec. 2 factor
+ * set in the plan's precision) and tables. */
 int64_t bfmht_plan_device_bytes(const bfmht_plan *plan);
 
 /* Bytes of workspace one apply or apply_transpose with this nrhs needs: two
- * ping-pong level buffers, each large enough for the longest level vector and
+ * ping-pong level buffers for the level vectors y_l of the Sec. 2 recursion
+ * (each level's products of V*, the transfer blocks R*, then U), each large enough for the longest level vector and
  * for f's n rows (apply_transpose first gathers f into tree order there);
  * -1 on a bad argument. */
 int64_t bfmht_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
 
-/* Copy the plan's factors and tables into dev_buf (device memory, at least
+/* The factor upload: copy the plan's factors (the Sec. 2 factor set) and tables into dev_buf (device memory, at least
  * bfmht_plan_device_bytes bytes, 256-byte aligned), on `stream`; synchronises
  * that stream, then frees the host staging copy.  The plan keeps dev_buf's
  * address; the caller keeps dev_buf alive until bfmht_plan_destroy.  A plan is
  * uploaded once; ESTATE on a second upload. */
 bfmht_status bfmht_plan_upload(bfmht_plan *plan, void *dev_buf, int64_t dev_bytes, void *stream);
 
-/* Synthesis f = Phi~ c.  c: device, m x nrhs (ld ldc); f: device, n x nrhs
+/* Synthesis f = Phi~ c (Sec. 1, eq. MHT-sum: point values from expansion
+ * coefficients), applied as the factored product of Sec. 2: level-0 bases,
+ * transfer levels 1..L, leaf bases.  c: device, m x nrhs (ld ldc); f: device, n x nrhs
  * (ld ldf), fully overwritten.  Element type double for F64, float otherwise.
  * ws: device workspace of at least bfmht_workspace_bytes(plan, nrhs) bytes,
  * 256-byte aligned.  c and f must not overlap ws or each other. */
 bfmht_status bfmht_apply(const bfmht_plan *plan, const void *c, int64_t ldc, void *f, int64_t ldf,
                          int32_t nrhs, void *ws, int64_t ws_bytes, void *stream);
 
-/* Analysis g = Phi~^T f: the exact transpose of bfmht_apply's steps, in
+/* Analysis g = Phi~^T f (Sec. 1: the adjoint maps point values to
+ * coefficients; Phi is real): the exact transpose of bfmht_apply's steps, in
  * reverse order.  f: device n x nrhs (ld ldf); g: device m x nrhs (ld ldg),
  * fully overwritten.  Same workspace rule as bfmht_apply. */
 bfmht_status bfmht_apply_transpose(const bfmht_plan *plan, const void *f, int64_t ldf, void *g,
@@ -200,7 +208,7 @@ bfmht_status bfmht_lsqr(const bfmht_plan *plan, const void *f, int64_t ldf, void
                         int32_t iters, void *rnorm, void *ws, int64_t ws_bytes, void *stream);
 int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
 
-/* Number of stages of one apply: L + 2 (level 0, the L transfer levels, the
+/* Number of stages of one apply (the levels of the Sec. 2 recursion): L + 2 (level 0, the L transfer levels, the
  * leaf stage), numbered in forward order; -1 for NULL.  Leading levels whose
  * blocks are all identities are folded into the next stage by single applies
  * (their tile shapes then have no effect). */
@@ -231,11 +239,17 @@ int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t co
  * BFMHT_BATCH_TRANSPOSE in mode) to in[i] (rows x nrhs[i], ld ldin[i]) and
  * overwrites out[i] (ld ldout[i]); instances with nrhs[i] == 0 are skipped.
  * All plans must be uploaded and share one precision.
- * Default: launch k runs the k-th stage of every instance at once (one work
- * item per output tile of each instance), so the number of launches is the
- * largest stage count in the batch, not the sum over instances (one launch per
- * stage position and kernel shape, each instance with its plan's tile shapes;
- * the per-stage segment tables travel as launch arguments); asynchronous.
+ * Instances that share one plan (the same handle) are applied as one block of
+ * columns: their inputs are packed side by side into the workspace and their
+ * outputs copied back, so the plan's factors are streamed once for all of them
+ * (results as from one apply per instance; a member with at most 4 columns
+ * then runs on the MFMA kernel instead of the vector-FMA one).
+ * Default: launch k runs the k-th stage of every unit (a shared-plan group or
+ * a single instance) at once, one work item per output tile, so the number of
+ * launches is the largest stage count in the batch, not the sum over instances
+ * (one launch per stage position and kernel shape, each unit with its plan's
+ * tile shapes; the per-stage segment tables travel as launch arguments);
+ * asynchronous.
  * BFMHT_BATCH_PERSISTENT: one launch of resident workgroups runs every stage of
  * every instance (64-row tiles, BFMHT_BATCH_WIDTH columns, the MFMA kernel for
  * every RHS count); workgroups take work items in stage order from per-XCD

@@ -131,7 +131,19 @@ def _c(a, dtype):
 
 
 def factors_struct(fs):
-    """Build the C struct from a factor-set dict; returns (struct, keepalive list)."""
+    """Build the C struct from a factor-set dict; returns (struct, keepalive list).
+    The C side reads every array to the length the tree implies (arity^L + 1
+    offsets, (L+1) arity^L ranks, ...); those lengths are checked here first,
+    since the library cannot see them."""
+    arity = int(fs["arity"]) if "arity" in fs else 2
+    L = int(fs["L"])
+    if arity in (2, 4) and 0 <= L and arity ** L <= (1 << 24):
+        nb = arity ** L
+        need = dict(perm_x=int(fs["n"]), xoff=nb + 1, koff=nb + 1, rank=(L + 1) * nb, ident=(L + 1) * nb,
+                    P_off=(L + 1) * nb, U_off=nb)
+        for k, ln in need.items():
+            if np.asarray(fs[k]).size != ln:
+                raise ValueError("factor set field %s has %d entries, the tree needs %d" % (k, np.asarray(fs[k]).size, ln))
     keep = dict(
         perm_x=_c(fs["perm_x"], np.int32), xoff=_c(fs["xoff"], np.int64), koff=_c(fs["koff"], np.int64),
         rank=_c(fs["rank"], np.int32).ravel(), ident=_c(fs["ident"], np.uint8).ravel(),

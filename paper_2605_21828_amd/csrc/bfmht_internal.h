@@ -134,6 +134,9 @@ int launch_bwd_stage(int prec, const StageArgs &a, int rows, int cols, void *str
 constexpr int64_t kFoldMaxCopies = 1 << 15;
 int launch_fold_sum(int esz, const void *src, int64_t lds, const int32_t *inv, int C, int64_t rows, void *dst,
                     int64_t ldd, int nrhs, void *stream);
+// dst[r][c] = src[r][c] for r < rows, c < cols (esz-byte elements).
+int launch_copy_block(int esz, const void *src, int64_t lds, int64_t rows, int cols, void *dst, int64_t ldd,
+                      void *stream);
 // dst[t] = src[perm[t]] for t < n (rows of nrhs elements of esz bytes).
 int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *perm, int64_t n, void *dst, int64_t ldd,
                        int nrhs, void *stream);

@@ -1195,6 +1195,33 @@ int launch_gather_rows(int esz, const void *src, int64_t lds, const int32_t *per
   return (int)hipGetLastError();
 }
 
+// Column block copy: dst[r][c] = src[r][c] for r < rows, c < cols (rows of
+// esz-byte elements with leading dimensions lds and ldd).  Packs the columns
+// of several instances that share one plan into one block, and unpacks them.
+template <typename T>
+__global__ __launch_bounds__(kNT) void copy_block_kernel(const T *src, int64_t lds, int64_t rows, int cols, T *dst,
+                                                         int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (int64_t)gridDim.x * kNT) {
+    const int64_t r = e / cols, c = e % cols;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
+int launch_copy_block(int esz, const void *src, int64_t lds, int64_t rows, int cols, void *dst, int64_t ldd,
+                      void *stream) {
+  const int64_t total = rows * cols;
+  if (total == 0) return 0;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + kNT - 1) / kNT, 8192);
+  if (esz == 8)
+    hipLaunchKernelGGL((copy_block_kernel<double>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const double *>(src), lds, rows, cols, static_cast<double *>(dst), ldd);
+  else
+    hipLaunchKernelGGL((copy_block_kernel<float>), dim3(grid), dim3(kNT), 0, (hipStream_t)stream,
+                       static_cast<const float *>(src), lds, rows, cols, static_cast<float *>(dst), ldd);
+  return (int)hipGetLastError();
+}
+
 // Sum of row copies: dst[r] = the C rows src[inv[r C + k]] summed pairwise in a
 // balanced tree over k (left to right within each pair), the order in which the
 // transposed identity levels it replaces add them.  slot[d] holds the pending

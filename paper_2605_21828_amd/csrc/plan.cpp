@@ -963,10 +963,22 @@ bfmht_status bfmht_plan_get_tile(const bfmht_plan *p, int32_t transpose, int32_t
 }  // extern "C"
 
 namespace {
+// The applies of a batch.  Instances that share one plan form one unit whose
+// right-hand sides are packed side by side into one block of columns (their
+// inputs copied in, their outputs copied back out), so the plan's factors are
+// streamed once for all of them; any other instance is a unit of its own.
+struct BatchUnit {
+  const bfmht_plan *p = nullptr;
+  int32_t nrhs = 0;                  // columns of the unit (summed over its members)
+  std::vector<int32_t> members;      // instance indices, in order
+  std::vector<int32_t> col;          // first packed column of each member
+  int64_t buf_off = 0;               // its two level buffers
+  int64_t in_off = -1, out_off = -1; // packed input and output blocks (-1: a single instance, used in place)
+};
 struct BatchLayout {
   int64_t total = 0;
   int32_t nseg = 0;
-  std::vector<int64_t> buf_off;  // per instance
+  std::vector<BatchUnit> units;
   int64_t table_off = 0;         // persistent launch: segment table, then its sync words
   int64_t sync_off = 0;
 };
@@ -989,23 +1001,100 @@ bfmht_status batch_layout(const bfmht_plan *const *plans, int32_t count, const i
   if (count < 0) return fail(BFMHT_EINVAL, "count < 0");
   if (count > 0 && (!plans || !nrhs)) return fail(BFMHT_EINVAL, "NULL plans or nrhs");
   L.nseg = 0;
-  L.buf_off.assign(count, 0);
+  L.units.clear();
   for (int32_t i = 0; i < count; ++i) {
     if (!plans[i]) return fail(BFMHT_EINVAL, "NULL plan in batch");
     if (nrhs[i] < 0) return fail(BFMHT_EINVAL, "nrhs < 0 in batch");
     if (plans[i]->prec != plans[0]->prec) return fail(BFMHT_EINVAL, "plans of a batch must share one precision");
-    if (nrhs[i] > 0) L.nseg += (int32_t)plans[i]->stages.size() + plans[i]->extra_parts;
+  }
+  // units: instances with columns, grouped by plan in order of first appearance
+  for (int32_t i = 0; i < count; ++i) {
+    if (nrhs[i] == 0) continue;
+    size_t u = 0;
+    while (u < L.units.size() && L.units[u].p != plans[i]) ++u;
+    if (u == L.units.size()) {
+      L.units.emplace_back();
+      L.units[u].p = plans[i];
+    }
+    BatchUnit &U = L.units[u];
+    if ((int64_t)U.nrhs + nrhs[i] >= (1ll << 31)) return fail(BFMHT_EINVAL, "too many columns for one plan in a batch");
+    U.col.push_back(U.nrhs);
+    U.members.push_back(i);
+    U.nrhs += nrhs[i];
   }
   int64_t cur = 0;
-  for (int32_t i = 0; i < count; ++i) {
-    L.buf_off[i] = cur;
-    if (nrhs[i] > 0) cur += 2 * level_buffer_bytes(plans[i], nrhs[i]);
+  for (BatchUnit &U : L.units) {
+    L.nseg += (int32_t)U.p->stages.size() + U.p->extra_parts;
+    U.buf_off = cur;
+    cur += 2 * level_buffer_bytes(U.p, U.nrhs);
+    if (U.members.size() > 1) {   // packed blocks of the unit's inputs and outputs (either direction)
+      const int64_t rows = std::max<int64_t>(U.p->n, U.p->m);
+      U.in_off = cur;
+      cur = align_up(cur + rows * U.nrhs * U.p->esz, 256);
+      U.out_off = cur;
+      cur = align_up(cur + rows * U.nrhs * U.p->esz, 256);
+    }
   }
   // the persistent launch's segment table and sync words (at most one segment per stage)
   L.table_off = align_up(cur, 256);
   L.sync_off = align_up(L.table_off + (int64_t)L.nseg * (int64_t)sizeof(PSegDev), 256);
   cur = L.sync_off + ((int64_t)L.nseg + kQueues + 1) * 4;
   L.total = std::max<int64_t>(align_up(cur, 256), 256);
+  return BFMHT_OK;
+}
+
+// Operands of each unit of a batch: a single instance's own, or the packed
+// blocks of a shared-plan unit, whose members' inputs are copied in here.
+struct UnitIO {
+  const void *in;
+  int64_t ldin;
+  void *out;
+  int64_t ldout;
+};
+
+bfmht_status prepare_units(const BatchLayout &L, const void *const *in, const int64_t *ldin, void *const *out,
+                           const int64_t *ldout, const int32_t *nrhs, bool fwd, char *ws, void *stream,
+                           std::vector<UnitIO> &io) {
+  io.clear();
+  for (const BatchUnit &U : L.units) {
+    const bfmht_plan *p = U.p;
+    if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
+    const int64_t rin = fwd ? p->m : p->n, rout = fwd ? p->n : p->m;
+    for (int32_t i : U.members) {
+      if ((!in[i] && rin > 0) || (!out[i] && rout > 0)) return fail(BFMHT_EINVAL, "NULL input or output in batch");
+      if ((rin > 0 && ldin[i] < nrhs[i]) || (rout > 0 && ldout[i] < nrhs[i]))
+        return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
+    }
+    if (U.members.size() == 1) {
+      const int32_t i = U.members[0];
+      io.push_back({in[i], ldin[i], out[i], ldout[i]});
+      continue;
+    }
+    char *pin = ws + U.in_off, *pout = ws + U.out_off;
+    for (size_t t = 0; t < U.members.size(); ++t) {
+      const int32_t i = U.members[t];
+      const int e = launch_copy_block((int)p->esz, in[i], ldin[i], rin, nrhs[i], pin + (int64_t)U.col[t] * p->esz,
+                                      U.nrhs, stream);
+      if (e) return fail(BFMHT_EHIP, std::string("batch packing launch: ") + hipGetErrorString((hipError_t)e));
+    }
+    io.push_back({pin, U.nrhs, pout, U.nrhs});
+  }
+  return BFMHT_OK;
+}
+
+// Copies the packed outputs of shared-plan units back to their members.
+bfmht_status finish_units(const BatchLayout &L, void *const *out, const int64_t *ldout, const int32_t *nrhs,
+                          bool fwd, char *ws, void *stream) {
+  for (const BatchUnit &U : L.units) {
+    if (U.members.size() == 1) continue;
+    const int64_t rout = fwd ? U.p->n : U.p->m;
+    for (size_t t = 0; t < U.members.size(); ++t) {
+      const int32_t i = U.members[t];
+      const int e = launch_copy_block((int)U.p->esz, ws + U.out_off + (int64_t)U.col[t] * U.p->esz, U.nrhs, rout,
+                                      nrhs[i], out[i], ldout[i], stream);
+      if (e) return fail(BFMHT_EHIP, std::string("batch unpacking launch: ") + hipGetErrorString((hipError_t)e));
+    }
+  }
   return BFMHT_OK;
 }
 
@@ -1017,31 +1106,30 @@ bfmht_status apply_persistent(const bfmht_plan *const *plans, int32_t count, con
                               bool fwd, int bn, const BatchLayout &L, char *ws, void *stream) {
   std::vector<PSegInfo> info;
   std::vector<PSegDev> segs;
-  for (int32_t i = 0; i < count; ++i) {
-    const bfmht_plan *p = plans[i];
-    if (nrhs[i] == 0) continue;
-    if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
-    if ((!in[i] && (fwd ? p->m : p->n) > 0) || (!out[i] && (fwd ? p->n : p->m) > 0))
-      return fail(BFMHT_EINVAL, "NULL input or output in batch");
-    if (((fwd ? p->m : p->n) > 0 && ldin[i] < nrhs[i]) || ((fwd ? p->n : p->m) > 0 && ldout[i] < nrhs[i]))
-      return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
-    char *base = ws + L.buf_off[i];
-    char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
+  std::vector<UnitIO> io;
+  bfmht_status st = prepare_units(L, in, ldin, out, ldout, nrhs, fwd, ws, stream, io);
+  if (st != BFMHT_OK) return st;
+  for (int32_t u = 0; u < (int32_t)L.units.size(); ++u) {
+    const BatchUnit &U = L.units[u];
+    const bfmht_plan *p = U.p;
+    char *base = ws + U.buf_off;
+    char *const buf[2] = {base, base + level_buffer_bytes(p, U.nrhs)};
     if (!fwd) {
-      const int e = gather_input(p, in[i], ldin[i], nrhs[i], buf, stream);
+      const int e = gather_input(p, io[u].in, io[u].ldin, U.nrhs, buf, stream);
       if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
     }
     const int S = (int)p->stages.size();
-    int pos = 0;   // position in the instance's stage sequence (a 4-ary transposed stage takes two)
+    int pos = 0;   // position in the unit's stage sequence (a 4-ary transposed stage takes two)
     for (int k = 0; k < S; ++k) {
       const int si = fwd ? k : S - 1 - k;
       if (fwd && p->stages[si].skip) continue;   // folded identity level: no items
       const int parts = fwd || p->stages[si].nbjob[1] == 0 ? 1 : 2;
       for (int part = 0; part < parts; ++part) {
         PSegDev d{};
-        d.a = stage_io(p, p->stages[si], fwd, kTileRows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf, part);
-        d.ny = (nrhs[i] + bn - 1) / bn;
-        info.push_back({i, pos++, (int64_t)(d.a.ntiles / kQueues) * d.ny});
+        d.a = stage_io(p, p->stages[si], fwd, kTileRows, io[u].in, io[u].ldin, io[u].out, io[u].ldout, U.nrhs, buf,
+                       part);
+        d.ny = (U.nrhs + bn - 1) / bn;
+        info.push_back({u, pos++, (int64_t)(d.a.ntiles / kQueues) * d.ny});
         segs.push_back(d);
       }
     }
@@ -1072,7 +1160,7 @@ bfmht_status apply_persistent(const bfmht_plan *const *plans, int32_t count, con
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(BFMHT_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
   if (err) return fail(BFMHT_EHIP, "persistent launch: a workgroup's wait for an earlier stage timed out");
-  return BFMHT_OK;
+  return finish_units(L, out, ldout, nrhs, fwd, ws, stream);
 }
 
 bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
@@ -1096,51 +1184,51 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
   const bool fwd = (mode & BFMHT_BATCH_TRANSPOSE) == 0;
   if (persistent) return apply_persistent(plans, count, in, ldin, out, ldout, nrhs, fwd, pwidth ? pwidth : 32, L,
                                           static_cast<char *>(ws), stream);
-  std::vector<std::vector<Segment>> per(count);
+  std::vector<UnitIO> io;
+  st = prepare_units(L, in, ldin, out, ldout, nrhs, fwd, static_cast<char *>(ws), stream, io);
+  if (st != BFMHT_OK) return st;
+  const int32_t nu = (int32_t)L.units.size();
+  std::vector<std::vector<Segment>> per(nu);
   size_t maxS = 0;
-  for (int32_t i = 0; i < count; ++i) {
-    const bfmht_plan *p = plans[i];
-    if (nrhs[i] == 0) continue;
-    if (!p->uploaded) return fail(BFMHT_ESTATE, "plan in batch not uploaded");
-    if ((!in[i] && (fwd ? p->m : p->n) > 0) || (!out[i] && (fwd ? p->n : p->m) > 0))
-      return fail(BFMHT_EINVAL, "NULL input or output in batch");
-    if (((fwd ? p->m : p->n) > 0 && ldin[i] < nrhs[i]) || ((fwd ? p->n : p->m) > 0 && ldout[i] < nrhs[i]))
-      return fail(BFMHT_EINVAL, "ld smaller than nrhs in batch");
-    char *base = static_cast<char *>(ws) + L.buf_off[i];
-    char *const buf[2] = {base, base + level_buffer_bytes(p, nrhs[i])};
+  for (int32_t u = 0; u < nu; ++u) {
+    const BatchUnit &U = L.units[u];
+    const bfmht_plan *p = U.p;
+    const int32_t b = U.nrhs;
+    char *base = static_cast<char *>(ws) + U.buf_off;
+    char *const buf[2] = {base, base + level_buffer_bytes(p, b)};
     if (!fwd) {
-      const int e = gather_input(p, in[i], ldin[i], nrhs[i], buf, stream);
+      const int e = gather_input(p, io[u].in, io[u].ldin, b, buf, stream);
       if (e) return fail(BFMHT_EHIP, std::string("input gather launch: ") + hipGetErrorString((hipError_t)e));
     }
     const int S = (int)p->stages.size();
-    const bool gemv = nrhs[i] <= kGemvMaxRhs && (p->prec == BFMHT_F32 || p->prec == BFMHT_F64);
+    const bool gemv = b <= kGemvMaxRhs && (p->prec == BFMHT_F32 || p->prec == BFMHT_F64);
     for (int k = 0; k < S; ++k) {
-     const int si = fwd ? k : S - 1 - k;
-     const int parts = fwd || p->stages[si].nbjob[1] == 0 ? 1 : 2;   // 4-ary transposed: two launches
-     for (int part = 0; part < parts; ++part) {
-      Segment sg{};
-      if (fwd && p->stages[si].skip) {   // folded identity level: an empty segment keeps the stage positions aligned
-        per[i].push_back(sg);
-        continue;
+      const int si = fwd ? k : S - 1 - k;
+      const int parts = fwd || p->stages[si].nbjob[1] == 0 ? 1 : 2;   // 4-ary transposed: two launches
+      for (int part = 0; part < parts; ++part) {
+        Segment sg{};
+        if (fwd && p->stages[si].skip) {   // folded identity level: an empty segment keeps the stage positions aligned
+          per[u].push_back(sg);
+          continue;
+        }
+        const int d = fwd ? 0 : 1;
+        const int rows = gemv ? kTileRows : p->rows[d][si];
+        sg.a = stage_io(p, p->stages[si], fwd, rows, io[u].in, io[u].ldin, io[u].out, io[u].ldout, b, buf, part);
+        sg.fwd = fwd ? 1 : 0;
+        if (gemv) {   // few right-hand sides: the vector-FMA kernel, as for a single apply
+          sg.fm = 0;
+          sg.bn = b <= 2 ? b : 4;
+          sg.ny = 1;
+        } else {
+          sg.fm = rows / kTileRows;
+          sg.bn = pick_cols(p->cols[d][si], b);
+          sg.ny = (b + sg.bn - 1) / sg.bn;
+        }
+        sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
+        per[u].push_back(sg);
       }
-      const int d = fwd ? 0 : 1;
-      const int rows = gemv ? kTileRows : p->rows[d][si];
-      sg.a = stage_io(p, p->stages[si], fwd, rows, in[i], ldin[i], out[i], ldout[i], nrhs[i], buf, part);
-      sg.fwd = fwd ? 1 : 0;
-      if (gemv) {   // few right-hand sides: the vector-FMA kernel, as for a single apply
-        sg.fm = 0;
-        sg.bn = nrhs[i] <= 2 ? nrhs[i] : 4;
-        sg.ny = 1;
-      } else {
-        sg.fm = rows / kTileRows;
-        sg.bn = pick_cols(p->cols[d][si], nrhs[i]);
-        sg.ny = (nrhs[i] + sg.bn - 1) / sg.bn;
-      }
-      sg.nitems = (int64_t)sg.a.ntiles * sg.ny;
-      per[i].push_back(sg);
-     }
     }
-    maxS = std::max(maxS, per[i].size());
+    maxS = std::max(maxS, per[u].size());
   }
   // Launch k runs the k-th stage of every instance, one launch per kernel kind
   // (MFMA tile shape bn x 64 fm, or the vector-FMA kernel for b columns), in
@@ -1165,9 +1253,9 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
       item[q] = 0;
       return BFMHT_OK;
     };
-    for (int32_t i = 0; i < count; ++i) {
-      if (k >= per[i].size() || per[i][k].nitems == 0) continue;
-      Segment sg = per[i][k];
+    for (int32_t u = 0; u < nu; ++u) {
+      if (k >= per[u].size() || per[u][k].nitems == 0) continue;
+      Segment sg = per[u][k];
       const int q = sg.fm == 0 ? 6 + (sg.bn == 1 ? 0 : (sg.bn == 2 ? 1 : 2))
                                : 2 * (sg.bn == 16 ? 0 : (sg.bn == 32 ? 1 : 2)) + (sg.fm == 2 ? 1 : 0);
       sg.item0 = item[q];
@@ -1183,7 +1271,7 @@ bfmht_status apply_batched(const bfmht_plan *const *plans, int32_t count, const 
       if (st != BFMHT_OK) return st;
     }
   }
-  return BFMHT_OK;
+  return finish_units(L, out, ldout, nrhs, fwd, static_cast<char *>(ws), stream);
 }
 }  // namespace
 

@@ -10,9 +10,20 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB_ASAN = os.path.join(ROOT, "paper_2605_21828_amd", "libbfmht_asan.so")
+SOURCES = [os.path.join(ROOT, "paper_2605_21828_amd", "csrc", f)
+           for f in os.listdir(os.path.join(ROOT, "paper_2605_21828_amd", "csrc"))] + \
+    [os.path.join(ROOT, "include", "bfmht.h")]
 
 
-@pytest.mark.skipif(not os.path.exists(LIB_ASAN), reason="AddressSanitizer build not present "
+def _asan_build_current():
+    """The sanitizer build exists and is newer than every source it is built from."""
+    if not os.path.exists(LIB_ASAN):
+        return False
+    t = os.path.getmtime(LIB_ASAN)
+    return all(os.path.getmtime(s) <= t for s in SOURCES if os.path.isfile(s))
+
+
+@pytest.mark.skipif(not _asan_build_current(), reason="no current AddressSanitizer build "
                     "(python -m paper_2605_21828_amd.build --asan)")
 def test_abi_tests_are_clean_under_address_sanitizer():
     sys.path.insert(0, ROOT)

@@ -278,3 +278,29 @@ def test_deep_identity_levels_beyond_fold_limit(gpu, deep_identity, prec, tol):
         p = Plan(fs, prec, max_nrhs=b)
         assert od.rel_err_cols(_np(p.apply(_t(c[:, :b], _dt(prec)))), y_ref[:, :b])[0] <= tol
         assert od.rel_err_cols(_np(p.apply_t(_t(f[:, :b], _dt(prec)))), g_ref[:, :b])[0] <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_shared_plan_instances_are_packed_into_one_apply(gpu, instances, prec, tol):
+    """Instances that share a plan are applied as one block of columns (inputs
+    packed, outputs unpacked): every output matches the oracle, and a member
+    with more than four columns equals its own single apply bit for bit (the
+    same MFMA sums per column)."""
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    fs_a, fs_b = instances[1], instances[5]
+    pa = Plan(fs_a, prec, max_nrhs=64)
+    pb = Plan(fs_b, prec, max_nrhs=64)
+    plans = [pa, pb, pa, pa, pb]
+    rhs = [7, 3, 2, 40, 19]
+    rng = np.random.default_rng(31)
+    sets = {id(pa): fs_a, id(pb): fs_b}
+    for transpose in (False, True):
+        xs = [rng.standard_normal(((p.n if transpose else p.m), b)) for p, b in zip(plans, rhs)]
+        outs = Batch(plans).run([_t(x, _dt(prec)) for x in xs], transpose=transpose)
+        for p, x, y, b in zip(plans, xs, outs, rhs):
+            fs = sets[id(p)]
+            ref = ob.apply_transpose(fs, x) if transpose else ob.apply(fs, x)
+            assert od.rel_err_cols(_np(y), ref)[0] <= tol, (transpose, b)
+            if b > 4:
+                single = p.apply_t(_t(x, _dt(prec))) if transpose else p.apply(_t(x, _dt(prec)))
+                assert np.array_equal(_np(single), _np(y)), (transpose, b)
