@@ -42,10 +42,10 @@ def host_memory():
         return {}
 
 
-def measured_traffic(workload):
-    """HBM bytes per forward FP32 stage launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or
-    None when the kernels have changed since the counters were taken."""
+def _counter_record(workload):
+    """The committed rocprofv3 counter summary of a workload
+    (profiles/hbm_traffic_<workload>.json), or None when it is missing or the
+    kernels have changed since its counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.json" % workload)
     try:
@@ -55,26 +55,26 @@ def measured_traffic(workload):
             cur = hashlib.sha1(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if d.get("kernels_hip_sha1") != cur:
-        return None
-    return d["fwd_per_dispatch"]["hbm_bytes"]
+    return d if d.get("kernels_hip_sha1") == cur else None
 
 
-def measured_mfma_busy(workload):
-    """MFMA busy percentage of the forward FP32 stage launches from the committed
-    rocprofv3 MfmaUtil summary, or None when the kernels have changed since."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "mfma_util_%s.json" % workload)
-    try:
-        with open(path) as f:
-            d = json.load(f)
-        with open(os.path.join(ROOT, "paper_2605_21828_amd", "csrc", "kernels.hip"), "rb") as f:
-            cur = hashlib.sha1(f.read()).hexdigest()
-    except (OSError, ValueError):
+def measured_traffic(workload, part="fwd", per="launch"):
+    """HBM bytes per stage launch (or per apply) of one measured part (e.g. the
+    forward FP32 apply): FETCH_SIZE and WRITE_SIZE scaled by what the same
+    counters read for a plain copy of known size.  None without a current record."""
+    d = _counter_record(workload)
+    if not d or part not in d:
         return None
-    if d.get("kernels_hip_sha1") != cur:
+    return d[part]["hbm_bytes_per_launch" if per == "launch" else "hbm_bytes_per_apply"]
+
+
+def measured_mfma_busy(workload, part="fwd"):
+    """MfmaUtil (matrix-core busy percent, duration-weighted over the part's
+    stage launches) from the same record, or None."""
+    d = _counter_record(workload)
+    if not d or part + "_mfma" not in d:
         return None
-    return d["fwd"]["mfma_busy_pct"]
+    return d[part + "_mfma"]["mfma_busy_pct"]
 
 
 # MI355X spec-sheet peaks: dense MFMA TFLOP/s per arithmetic type and HBM GB/s.
@@ -324,7 +324,9 @@ def bench_batched(args):
                      "t_roof_ms": t_roof * 1e3, "t_roof_mfma_bound_ms": t_mfma * 1e3,
                      "t_roof_hbm_bound_ms": t_hbm * 1e3,
                      "note": "sum over instances of max(HBM time, MFMA time); achieved = frac x peak of the "
-                             "dominant bound",
+                             "dominant bound; traffic: counter bytes of one batched forward call",
+                     "traffic_per_batched_apply": measured_traffic("batched32", "fwd", per="apply"),
+                     "mfma_busy_pct_counter": measured_mfma_busy("batched32", "fwd"),
                      "kernel": "batched_stage_kernel<1> (all launches of one batched FP32 apply)"},
         "cpu_baseline": base,
         "extra": {"batched_apply_ms": ms_fwd, "one_by_one_apply_ms": ms_seq,
@@ -409,6 +411,11 @@ def bench_sphere(args):
         base = None
     t_main = rec[main]["apply_ms"]
     roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=int(fs["L"]) + 2 - folded_levels(fs))
+    part = "fwd" if main == "bf16x3" else main + "_fwd"   # the counter record's headline part is BF16X3
+    roof["traffic"] = measured_traffic("sphere40962", part)
+    roof["traffic_unit"] = "bytes per launch"
+    roof["mfma_busy_pct_counter"] = measured_mfma_busy("sphere40962", part)
+    roof["level_vector_bytes_per_launch"] = level_bytes(fs, b, 4) / (int(fs["L"]) + 2 - folded_levels(fs))
     res = {
         "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
         "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
@@ -724,6 +731,67 @@ def bench_copy(args):
                       "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def counter_run(args):
+    """A fixed number of applies of one direction and precision and nothing
+    else (no timing, no oracle), for hardware-counter passes under rocprofv3:
+    the counter totals divided by the printed apply count give per-apply
+    figures.  Workloads: iid65536, iid131072 (one RHS, the least-squares fit's
+    shape), sphere40962 (256 RHS) and batched32 (one batched call per apply).
+    Tile shapes come from the autotuner's cache when --cache is given."""
+    import torch
+
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Batch, Plan
+    from paper_2605_21828_amd.factor import io as fio
+
+    prec, fwd, count = args.counter_precision, args.counter_direction == "fwd", args.counter_applies
+    dev = torch.device("cuda:0")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    if args.workload == "batched32":
+        spec = wl.BATCHED
+        inst = wl.batched_instances(spec)
+        plans = {}
+        for side in sorted({s for s, _ in inst}):
+            fs = fio.fourier_factors(wl.grid_points(side), side * side // 4, spec["leaf"], spec["tol"],
+                                     workers=args.workers, cache=args.cache)[0]
+            plans[side] = Plan(fs, prec, max_nrhs=spec["max_nrhs"], device=dev)
+        ps = [plans[s] for s, _ in inst]
+        xs = [torch.randn(((p.m if fwd else p.n), b), dtype=dt, device=dev) for p, (_, b) in zip(ps, inst)]
+        batch = Batch(ps)
+        outs = [torch.empty(((p.n if fwd else p.m), b), dtype=dt, device=dev) for p, (_, b) in zip(ps, inst)]
+        if args.cache and not args.no_tune:
+            from paper_2605_21828_amd.autotune import tune_batch
+            tune_batch(batch, xs, transpose=not fwd, log=log)
+        run = lambda: batch.launch(xs, outs, not fwd)   # noqa: E731
+        launches = None
+    else:
+        if args.workload == "sphere40962":
+            spec = wl.SPHERE
+            fs, _ = fio.sphere_factors(spec["level"], spec["wid"], spec["m"], spec["leaf"], spec["tol"],
+                                       workers=args.workers, cache=args.cache)
+            b = spec["nrhs"]
+        else:
+            w = wl.WORKLOADS[args.workload]
+            fs, _ = fio.fourier_factors(wl.points_for(w), w["m"], w["leaf"], w["tol"], workers=args.workers,
+                                        cache=args.cache, arity=args.arity)
+            b = w["nrhs"]
+        p = Plan(fs, prec, max_nrhs=b, device=dev)
+        if args.cache and not args.no_tune:
+            from paper_2605_21828_amd.autotune import tune_plan
+            tune_plan(p, fs, b, use_cache=True, log=log)
+        x = torch.randn(((p.m if fwd else p.n), b), dtype=dt, device=dev)
+        y = torch.empty(((p.n if fwd else p.m), b), dtype=dt, device=dev)
+        run = (lambda: p.apply(x, out=y)) if fwd else (lambda: p.apply_t(x, out=y))
+        launches = int(fs["L"]) + 2 - (folded_levels(fs) if fwd else 0)
+    run()
+    torch.cuda.synchronize()
+    for _ in range(count):
+        run()
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_run": args.workload, "precision": prec, "direction": args.counter_direction,
+                      "applies": count + 1, "stage_launches_per_apply": launches}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -741,10 +809,16 @@ def main():
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     ap.add_argument("--arity", type=int, default=2, choices=(2, 4),
                     help="tree arity of the nonuniform-square workloads (4: quadtree and 4-ary mode tree)")
+    ap.add_argument("--counter-applies", type=int, default=0,
+                    help="counter run: this many applies (plus one) of one direction and precision, nothing else")
+    ap.add_argument("--counter-direction", default="fwd", choices=("fwd", "bwd"))
+    ap.add_argument("--counter-precision", default="f32", choices=("f64", "f32", "bf16x2", "bf16x3"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.counter_applies > 0:
+        return counter_run(args)
     if args.workload == "batched32":
         return bench_batched(args)
     if args.workload == "copy":
@@ -767,6 +841,7 @@ def main():
 
     w = wl.WORKLOADS[args.workload]
     n, m, b = w["n"], w["m"], w["nrhs"]
+    counter_key = args.workload if args.arity == 2 else "%s_arity%d" % (args.workload, args.arity)
     pts = wl.points_for(w)
     log("building factors: n=%d m=%d leaf=%d tol=%g arity=%d" % (n, m, w["leaf"], w["tol"], args.arity))
     fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
@@ -850,7 +925,9 @@ def main():
         rec = {"apply_ms": t_f, "apply_transpose_ms": t_b,
                "speedup_vs_fp32": (ms_fwd + ms_bwd) / (t_f + t_b),
                "plan_device_GB": pv.device_bytes / 1e9, "tile_shapes": shapes,
-               "roofline": roofline_for(prec, pv.stored_fwd, n, m, b, t_f, launches)}
+               "roofline": dict(roofline_for(prec, pv.stored_fwd, n, m, b, t_f, launches),
+                                traffic=measured_traffic(counter_key, prec + "_fwd"),
+                                mfma_busy_pct_counter=measured_mfma_busy(counter_key, prec + "_fwd"))}
         if prec == "f64":
             y64 = yv.clone()
         else:
@@ -889,9 +966,9 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
                    "L": int(fs["L"]), "arity": args.arity, "step": "apply + apply_transpose"},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / peak, "traffic": measured_traffic(counter_key),
                      "traffic_unit": "bytes per launch",
-                     "mfma_busy_pct_counter": measured_mfma_busy(args.workload),
+                     "mfma_busy_pct_counter": measured_mfma_busy(counter_key),
                      "alg_bytes_per_launch": alg_bytes32 / launches,
                      # level vectors written by one stage and read by the next: not
                      # algorithmic (intermediate), reported beside it
