@@ -259,8 +259,10 @@ int64_t bfmht_batched_workspace_bytes(const bfmht_plan *const *plans, int32_t co
  * currently switched off and returns EINVAL (its GPU run did not finish in
  * time); the per-stage launches are the batched path.
  * ws: device workspace, 256-byte aligned, at least bfmht_batched_workspace_bytes;
- * it holds each instance's level buffers (and the persistent launch's tables),
- * so calls that overlap on one workspace race.  EINVAL on unknown mode bits. */
+ * it holds each unit's level buffers, the packed blocks of shared-plan units
+ * (and the persistent launch's tables), so calls that overlap on one workspace
+ * race.  No output may overlap an input, another output or ws.  EINVAL on
+ * unknown mode bits. */
 bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, const void *const *in,
                                  const int64_t *ldin, void *const *out, const int64_t *ldout, const int32_t *nrhs,
                                  int32_t mode, void *ws, int64_t ws_bytes, void *stream);
