@@ -18,6 +18,10 @@ Modules
              formulation used to pin O2 at tiny sizes
   lsqr       LSQR (Paige and Saunders), the least-squares solver the inverse
              transform uses (Sec. 7.1, eq. inverse-MHT)
+  interp     column interpolative decomposition of one block by column-pivoted
+             QR (Sec. 2, the low-rank factorization each block takes)
+  factorize  the butterfly factorization of a dense Phi with column IDs (Sec. 2,
+             Alg. "Butterfly factorization"; Sec. 4 streaming order noted)
   fem        element-by-element linear finite-element stiffness and lumped mass
              on a triangle mesh, a second formulation of the cotangent Laplacian
 
