@@ -717,6 +717,184 @@ def bench_latency(args):
     print(json.dumps(res), flush=True)
 
 
+def _qr_flops(fs):
+    """Algorithmic flops of the column IDs of a factor set: a Householder QR
+    stopped after k = rank steps costs sum_{j<k} 4 (M - j)(K - j) on an M x K
+    block (the reflector's dot product and update of every remaining column);
+    blocks without rows or columns cost nothing."""
+    L, nb = int(fs["L"]), 2 ** int(fs["L"])
+    xoff, koff, rank = fs["xoff"], fs["koff"], fs["rank"]
+    tot = 0.0
+    for lvl in range(L + 1):
+        nf = 2 ** (L - lvl)
+        for q in range(nb):
+            i, j = divmod(q, nf)
+            M = int(xoff[(i + 1) * nf] - xoff[i * nf]) if lvl else int(xoff[-1])
+            K = int(koff[j + 1] - koff[j]) if lvl == 0 else int(rank[lvl - 1][(i // 2) * 2 * nf + 2 * j] +
+                                                                 rank[lvl - 1][(i // 2) * 2 * nf + 2 * j + 1])
+            k = np.arange(int(rank[lvl][q]), dtype=np.float64)
+            if M and K:
+                tot += float(np.sum(4.0 * (M - k) * (K - k)))
+    return tot
+
+
+def _block_skeletons(fs):
+    """Per level, per block: (input columns, local skeleton) read back from a
+    stored factor set (the unit columns of P; every column of an identity block)."""
+    L, nb = int(fs["L"]), 2 ** int(fs["L"])
+    koff = fs["koff"]
+    skel, out = [None] * nb, []
+    for lvl in range(L + 1):
+        nf = 2 ** (L - lvl)
+        new, cur = [None] * nb, []
+        for q in range(nb):
+            i, j = divmod(q, nf)
+            cols = np.arange(koff[j], koff[j + 1]) if lvl == 0 else \
+                np.concatenate([skel[(i // 2) * 2 * nf + 2 * j], skel[(i // 2) * 2 * nf + 2 * j + 1]])
+            r = int(fs["rank"][lvl][q])
+            if fs["ident"][lvl][q]:
+                Jl = np.arange(cols.size)
+            elif r == 0:
+                Jl = np.zeros(0, np.int64)
+            else:
+                o = int(fs["P_off"][lvl][q])
+                P = fs["P"][o:o + r * cols.size].reshape(r, cols.size)
+                unit = (P == 1.0) & (np.abs(P).sum(axis=0) == 1.0)[None, :]
+                Jl = np.array([int(np.flatnonzero(unit[t])[0]) for t in range(r)], np.int64)
+            new[q] = cols[Jl]
+            cur.append((cols, Jl))
+        out.append(cur)
+        skel = new
+    return out
+
+
+def bench_build(args):
+    """The butterfly factorization on the GPU (FP64 column IDs: block formation,
+    pivoted QR and interpolation matrices in HIP kernels) on the i.i.d. square:
+    seconds per build, against the host builder (NumPy/SciPy on the host's
+    cores) and the oracle's column ID timed on sampled blocks."""
+    import torch
+
+    from oracle import dense as od
+    from oracle import interp as oi
+    from oracle import modes as om
+    from paper_2605_21828_amd import workloads as wl
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor import io as fio
+    from paper_2605_21828_amd.factor import trees
+    from paper_2605_21828_amd.factor.device_build import build_factors_device, fourier_tables
+    from paper_2605_21828_amd.factor.fourier import real_modes
+
+    wname = args.workload[len("build_"):]
+    w = wl.WORKLOADS[wname]
+    n, m, leaf, tol = w["n"], w["m"], w["leaf"], w["tol"]
+    pts = wl.points_for(w)
+    L = trees.depth_for(n, leaf)
+    perm, xoff = trees.box_bisection_tree(pts, L)
+    koff = trees.frequency_tree(m, L)
+    modes = real_modes(m)
+    dev = torch.device("cuda:0")
+    # warm-up: a small build loads the kernels and grows no buffer of the timed one
+    sw = wl.iid_points(99, 2048)
+    sL = trees.depth_for(2048, 64)
+    sp, sx = trees.box_bisection_tree(sw, sL)
+    build_factors_device(fourier_tables(sw, real_modes(512), sp, dev), 2048, 512, sp, sx,
+                         trees.frequency_tree(512, sL), sL, tol)
+    torch.cuda.synchronize()
+    log("device build: n=%d m=%d leaf=%d tol=%g L=%d" % (n, m, leaf, tol, L), host_memory())
+    events = []
+    t0 = time.perf_counter()
+    tabs = fourier_tables(pts, modes, perm, dev)
+    fs = build_factors_device(tabs, n, m, perm, xoff, koff, L, tol, events=events,
+                              log=lambda s: log("  level", s))
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    id_ms = sum(a.elapsed_time(b) for a, b in events)
+    flops = _qr_flops(fs)
+    log("device build %.2f s (column-ID kernels %.1f ms, %.3g flop)" % (t_dev, id_ms, flops), host_memory())
+    del tabs
+    # accuracy: FP64 synthesis of the device-built set on sampled rows against the dense transform
+    b = 2
+    c = wl.coefficients(w["wid"], m, b)
+    p64 = Plan(fs, "f64", max_nrhs=b, device=dev)
+    y = p64.apply(torch.tensor(c, dtype=torch.float64, device=dev)).cpu().numpy()
+    rows = wl.sample_indices(w["wid"], n, 256)
+    omodes = om.fourier_modes(m)
+    synth_err = od.rel_err_cols(y[rows], od.fourier_synthesis_rows(pts, omodes, rows, c))[0]
+    del p64
+    host = None
+    if args.host_build:
+        log("host build (%d workers)" % args.workers)
+        t1 = time.perf_counter()
+        fh, _ = fio.fourier_factors(pts, m, leaf, tol, workers=args.workers, cache=False)
+        t_host = time.perf_counter() - t1
+        same_rank = float(np.mean(fh["rank"] == fs["rank"]))
+        same_skel = bool(np.array_equal(fh["skel_L"], fs["skel_L"]))
+        host = {"seconds": t_host, "workers": args.workers, "blocks_with_equal_rank": same_rank,
+                "final_skeletons_equal": same_skel, "stored_entries_host": fio.stored_entries(fh),
+                "speedup_device_vs_host": t_host / t_dev}
+        log("host build %.1f s: %.1fx the device build; equal ranks on %.4f of the blocks" % (
+            t_host, t_host / t_dev, same_rank))
+        del fh
+    base, sample_check = None, None
+    if not args.no_cpu_baseline:
+        # oracle column IDs of sampled blocks of every level (about 20 s), scaled
+        # to all blocks of each level; the sampled blocks also check the device's
+        # skeletons and interpolation matrices
+        rng = wl.rng(w["wid"], 5)
+        per = _block_skeletons(fs)
+        nb = 2 ** L
+        t_or, t_est, checked, agree, p_err = 0.0, 0.0, 0, 0, 0.0
+        for lvl in range(L + 1):
+            nf = 2 ** (L - lvl)
+            qs = rng.choice(nb, 2, replace=False)
+            tl = 0.0
+            for q in qs:
+                i, j = divmod(int(q), nf)
+                cols, Jl = per[lvl][q]
+                if not cols.size:
+                    continue
+                blk_rows = perm[xoff[i * nf]:xoff[(i + 1) * nf]]
+                A = om.phi(pts[blk_rows], omodes[cols])
+                t1 = time.perf_counter()
+                Jo, Po, ido = oi.column_id(A, tol)
+                tl += time.perf_counter() - t1
+                checked += 1
+                agree += int(np.array_equal(Jo, Jl))
+                if Po is not None and Po.size and not fs["ident"][lvl][q]:
+                    r = int(fs["rank"][lvl][q])
+                    o = int(fs["P_off"][lvl][q])
+                    Pd = fs["P"][o:o + r * cols.size].reshape(r, cols.size)
+                    if Pd.shape == Po.shape:
+                        p_err = max(p_err, float(np.abs(Pd - Po).max() / max(1.0, np.abs(Po).max())))
+            t_or += tl
+            t_est += tl * nb / len(qs)
+        base = {"value": t_est, "unit": "s", "cores": _blas_threads(), "kind": "oracle",
+                "sample": "oracle column ID (SciPy pivoted QR, FP64) of 2 blocks per level, %.1f s, scaled to "
+                          "all %d blocks of each level (block formation not counted)" % (t_or, nb)}
+        sample_check = {"blocks": checked, "same_skeleton": agree, "max_rel_P_diff": p_err}
+    peak = 78.6   # FP64 vector FMA, TFLOP/s
+    tf = flops / (id_ms * 1e-3) / 1e12 if id_ms > 0 else 0.0
+    res = {
+        "metric": "butterfly factorization time on the device (FP64 column IDs)",
+        "value": t_dev, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_dev * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "leaf": leaf, "tol": tol, "L": L,
+                   "step": "tables, every level's blocks formed and decomposed, leaf bases, factor set packed"},
+        "roofline": {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                     "traffic": None, "kernel": "cpqr_kernel",
+                     "note": "Householder QR flops (4 (M-j)(K-j) per step, rank steps per block) over the "
+                             "column-ID launches' event time; level-2 updates stream each block once per step, "
+                             "so the launches are bound by that traffic rather than the FMA rate"},
+        "cpu_baseline": base,
+        "extra": {"column_id_kernel_ms": id_ms, "qr_flops": flops, "stored_entries": fio.stored_entries(fs),
+                  "levels": [[s[0], s[1], s[2], s[3], s[4], s[5]] for s in fs["build_stats"].tolist()],
+                  "fp64_synthesis_rel_err_256_rows": synth_err, "host_build": host,
+                  "oracle_sample_check": sample_check, "host_memory_at_end": host_memory()},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_copy(args):
     """Calibration: a plain device copy of a known number of bytes (for HBM byte counters)."""
     import torch
@@ -809,6 +987,8 @@ def main():
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     ap.add_argument("--arity", type=int, default=2, choices=(2, 4),
                     help="tree arity of the nonuniform-square workloads (4: quadtree and 4-ary mode tree)")
+    ap.add_argument("--host-build", action="store_true",
+                    help="build_* workloads: also time the host builder on the same inputs")
     ap.add_argument("--counter-applies", type=int, default=0,
                     help="counter run: this many applies (plus one) of one direction and precision, nothing else")
     ap.add_argument("--counter-direction", default="fwd", choices=("fwd", "bwd"))
@@ -831,6 +1011,8 @@ def main():
         return bench_lsq(args)
     if args.workload == "sphere40962":
         return bench_sphere(args)
+    if args.workload.startswith("build_"):
+        return bench_build(args)
 
     import torch
 

@@ -7,8 +7,9 @@
  * Phi^T (Sec. 1, the adjoint transform).  Phi is given as a row-wise butterfly
  * factor set built on the host (Sec. 2, Alg. "Butterfly factorization" and the
  * set it returns: a basis per frequency leaf, a transfer block per block pair at
- * levels 1..L, a column basis per space leaf).  Construction stays on the host
- * in FP64; this library only uploads and applies the factors.
+ * levels 1..L, a column basis per space leaf).  The factors are computed in
+ * FP64, on the host or with the batched device calls near the end of this
+ * file; the apply calls upload and apply them.
  *
  * Conventions
  *  - Both trees are complete binary trees of depth L (or 4-ary, see arity
@@ -284,6 +285,63 @@ bfmht_status bfmht_apply_batched(const bfmht_plan *const *plans, int32_t count, 
 #define BFMHT_NOALLOC_WORKSPACE_BYTES (256ll << 20)
 bfmht_status bfmht_apply_noalloc(const bfmht_plan *plan, const void *c, int64_t ldc, void *f, int64_t ldf,
                                  int32_t nrhs, void *stream);
+
+/* ---- The factorization on the device (FP64) ----
+ * Every block that the butterfly factorization compresses is a submatrix of
+ * Phi: with column interpolative decompositions the previous level's column
+ * basis restricted to a space node is Phi at the previous skeleton columns
+ * (Sec. 2, Alg. "Butterfly factorization"; Sec. 4, the streaming variant that
+ * only ever evaluates such blocks).  A level is then a batch of independent
+ * tall blocks of uneven size; these calls form such a batch from tables and
+ * compute the column ID of every block.  The caller orders the levels.
+ *
+ * Metadata arguments are HOST arrays, checked on the host and staged into the
+ * device workspace ws (at least bfmht_factor_meta_bytes(count, col_off[count])
+ * bytes, 256-byte aligned); each call synchronises `stream` once after staging
+ * (so the host arrays may be freed on return) and leaves its kernels running
+ * asynchronously.  Block b has rows[b] rows and K_b = col_off[b+1] - col_off[b]
+ * columns (col_off[0] = 0, nondecreasing) and lives column-major (ld = rows[b])
+ * at a + a_off[b], inside a_len doubles.  count == 0 is a no-op.  Blocks must
+ * not overlap (not checked). */
+int64_t bfmht_factor_meta_bytes(int32_t count, int64_t total_cols);
+
+/* Form the blocks: entry (t, s) of block b is
+ *   tab0[ta[g] * ld0 + row0[b] + t] * tab1[tb[g] * ld1 + row0[b] + t],  g = col_off[b] + s.
+ * tab0 / tab1: device, w0 / w1 columns of ld0 / ld1 rows (points in tree
+ * order).  For the Fourier matrix the two tables hold cos and sin of k x per
+ * coordinate (Sec. 1, eq. 2D-DFT); for a dense Phi (Sec. 7's eigenvectors)
+ * tab0 = Phi^T in tree order and tab1 one row of ones (tb = 0).
+ * EINVAL if a block's rows leave [0, min(ld0, ld1)), a table column index is
+ * out of range, or a block leaves a. */
+bfmht_status bfmht_form_blocks(int32_t count, const int64_t *row0, const int64_t *rows, const int64_t *col_off,
+                               const int32_t *ta, const int32_t *tb, const int64_t *a_off, const double *tab0,
+                               int64_t ld0, int64_t w0, const double *tab1, int64_t ld1, int64_t w1, double *a,
+                               int64_t a_len, void *ws, int64_t ws_bytes, void *stream);
+
+/* Column IDs of the blocks (Sec. 2: the low-rank factorization of every block,
+ * here A ~ A(:, J) P): column-pivoted Householder QR of each block in place (the
+ * block is overwritten by R and the reflectors), pivoting on the largest
+ * remaining column norm (first column on ties), stopped at the first pivot
+ * whose norm is not above tol times the first pivot's.  Outputs (device):
+ * rank[b] = k, the number of columns kept (0 for an all-zero block);
+ * piv[col_off[b] + s] = the block column (0 .. K_b-1) at pivot position s, for
+ * all K_b positions; J = piv[0 .. k).  EINVAL on tol < 0 or a block wider than
+ * local memory holds (about 5000 columns). */
+bfmht_status bfmht_column_id(int32_t count, const int64_t *rows, const int64_t *col_off, const int64_t *a_off,
+                             double *a, int64_t a_len, double tol, int32_t *rank, int32_t *piv, void *ws,
+                             int64_t ws_bytes, void *stream);
+
+/* The interpolation matrices after bfmht_column_id, on the same a and piv:
+ * for every block with p_off[b] >= 0, P (rank[b] x K_b, row-major, at
+ * p + p_off[b], inside p_len doubles) with P(:, piv[s]) = e_s for s < k and
+ * P(:, piv[s]) = column s - k of R11^-1 R12 for s >= k (back substitution on
+ * the triangular factor).  rank, p_off: host arrays (rank as bfmht_column_id
+ * returned it); blocks with p_off[b] < 0 are skipped (the caller skips blocks
+ * that keep every column, whose P is the identity). */
+bfmht_status bfmht_id_coefficients(int32_t count, const int64_t *rows, const int64_t *col_off, const int64_t *a_off,
+                                   const double *a, int64_t a_len, const int32_t *rank, const int32_t *piv,
+                                   const int64_t *p_off, double *p, int64_t p_len, void *ws, int64_t ws_bytes,
+                                   void *stream);
 
 /* Free the plan's host memory.  Does not touch device memory.  NULL is a no-op. */
 void bfmht_plan_destroy(bfmht_plan *plan);

@@ -45,6 +45,7 @@ EXPORTED = [
     "bfmht_batched_workspace_bytes", "bfmht_apply_batched",
     "bfmht_apply_scaled", "bfmht_apply_transpose_scaled", "bfmht_lsqr", "bfmht_lsqr_workspace_bytes",
     "bfmht_plan_create_ex", "bfmht_plan_stored_entries", "bfmht_apply_noalloc",
+    "bfmht_factor_meta_bytes", "bfmht_form_blocks", "bfmht_column_id", "bfmht_id_coefficients",
 ]
 
 NOALLOC_WORKSPACE_BYTES = 256 << 20  # BFMHT_NOALLOC_WORKSPACE_BYTES
@@ -108,6 +109,16 @@ def load_library(path=LIB_PATH):
     lib.bfmht_apply_batched.argtypes = [pp, i32, pp, ctypes.POINTER(i64), pp, ctypes.POINTER(i64),
                                         ctypes.POINTER(i32), i32, vp, i64, vp]
     lib.bfmht_apply_batched.restype = ctypes.c_int
+    I64P, I32P, DP = ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)
+    lib.bfmht_factor_meta_bytes.argtypes = [i32, i64]
+    lib.bfmht_factor_meta_bytes.restype = i64
+    lib.bfmht_form_blocks.argtypes = [i32, I64P, I64P, I64P, I32P, I32P, I64P, vp, i64, i64, vp, i64, i64, vp, i64,
+                                      vp, i64, vp]
+    lib.bfmht_form_blocks.restype = ctypes.c_int
+    lib.bfmht_column_id.argtypes = [i32, I64P, I64P, I64P, vp, i64, ctypes.c_double, vp, vp, vp, i64, vp]
+    lib.bfmht_column_id.restype = ctypes.c_int
+    lib.bfmht_id_coefficients.argtypes = [i32, I64P, I64P, I64P, vp, i64, I32P, vp, I64P, vp, i64, vp, i64, vp]
+    lib.bfmht_id_coefficients.restype = ctypes.c_int
     return lib
 
 
@@ -260,6 +271,57 @@ def bfmht_apply_batched(plans, ins, ldin, outs, ldout, nrhs, mode, ws_ptr, ws_by
     _check(lib.bfmht_apply_batched(_arr(vp, plans), len(plans), _arr(vp, ins), _arr(i64, ldin), _arr(vp, outs),
                                    _arr(i64, ldout), _arr(i32, nrhs), int(mode), ws_ptr, int(ws_bytes),
                                    stream), "bfmht_apply_batched")
+
+
+def _host(a, dtype, n, name):
+    """Contiguous host copy of a metadata array, checked to hold n entries."""
+    a = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    if a.ndim != 1 or a.size != n:
+        raise ValueError("%s: expected %d entries, got shape %s" % (name, n, a.shape))
+    return a
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def bfmht_factor_meta_bytes(count, total_cols):
+    return lib.bfmht_factor_meta_bytes(int(count), int(total_cols))
+
+
+def bfmht_form_blocks(row0, rows, col_off, ta, tb, a_off, tab0_ptr, ld0, w0, tab1_ptr, ld1, w1, a_ptr, a_len,
+                      ws_ptr, ws_bytes, stream=0):
+    """Host metadata arrays (numpy), device tables, blocks and workspace (addresses)."""
+    count = len(rows)
+    col_off = _host(col_off, np.int64, count + 1, "col_off")
+    tc = int(col_off[-1]) if count else 0
+    row0, rows, a_off = (_host(x, np.int64, count, nm) for x, nm in ((row0, "row0"), (rows, "rows"), (a_off, "a_off")))
+    ta, tb = _host(ta, np.int32, tc, "ta"), _host(tb, np.int32, tc, "tb")
+    I64, I32 = ctypes.c_int64, ctypes.c_int32
+    _check(lib.bfmht_form_blocks(count, _ptr(row0, I64), _ptr(rows, I64), _ptr(col_off, I64), _ptr(ta, I32),
+                                 _ptr(tb, I32), _ptr(a_off, I64), tab0_ptr, int(ld0), int(w0), tab1_ptr, int(ld1),
+                                 int(w1), a_ptr, int(a_len), ws_ptr, int(ws_bytes), stream), "bfmht_form_blocks")
+
+
+def bfmht_column_id(rows, col_off, a_off, a_ptr, a_len, tol, rank_ptr, piv_ptr, ws_ptr, ws_bytes, stream=0):
+    count = len(rows)
+    col_off = _host(col_off, np.int64, count + 1, "col_off")
+    rows, a_off = _host(rows, np.int64, count, "rows"), _host(a_off, np.int64, count, "a_off")
+    I64 = ctypes.c_int64
+    _check(lib.bfmht_column_id(count, _ptr(rows, I64), _ptr(col_off, I64), _ptr(a_off, I64), a_ptr, int(a_len),
+                               float(tol), rank_ptr, piv_ptr, ws_ptr, int(ws_bytes), stream), "bfmht_column_id")
+
+
+def bfmht_id_coefficients(rows, col_off, a_off, a_ptr, a_len, rank, piv_ptr, p_off, p_ptr, p_len, ws_ptr, ws_bytes,
+                          stream=0):
+    count = len(rows)
+    col_off = _host(col_off, np.int64, count + 1, "col_off")
+    rows, a_off = _host(rows, np.int64, count, "rows"), _host(a_off, np.int64, count, "a_off")
+    rank, p_off = _host(rank, np.int32, count, "rank"), _host(p_off, np.int64, count, "p_off")
+    I64, I32 = ctypes.c_int64, ctypes.c_int32
+    _check(lib.bfmht_id_coefficients(count, _ptr(rows, I64), _ptr(col_off, I64), _ptr(a_off, I64), a_ptr, int(a_len),
+                                     _ptr(rank, I32), piv_ptr, _ptr(p_off, I64), p_ptr, int(p_len), ws_ptr,
+                                     int(ws_bytes), stream), "bfmht_id_coefficients")
 
 
 class Plan:

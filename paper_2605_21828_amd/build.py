@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfmht.so")
 LIB_ASAN = os.path.join(HERE, "libbfmht_asan.so")
 ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
-SOURCES = ["plan.cpp", "kernels.hip", "lsqr.hip", "noalloc.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "lsqr.hip", "noalloc.hip", "factor.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -129,8 +129,14 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
             U_list.append(np.ascontiguousarray(U))
         else:
             U_list.append(np.zeros((rows.size, cols.size)))
-    # Pack the blocks into one array each, releasing every block once it is
-    # copied, so the peak host memory stays near one copy of the factors.
+    return pack_factor_set(n, m, L, tol, a_, perm_x, xoff, koff, rank, ident, P_blocks, U_list, J_prev, stats)
+
+
+def pack_factor_set(n, m, L, tol, a_, perm_x, xoff, koff, rank, ident, P_blocks, U_list, J_last, stats):
+    """Pack per-block P and leaf U arrays into the factor-set dict (schema in
+    io.py), releasing every block once it is copied, so the peak host memory
+    stays near one copy of the factors."""
+    nb = a_ ** L
     P_off = np.full((L + 1, nb), -1, dtype=np.int64)
     off = 0
     for lvl in range(L + 1):
@@ -162,7 +168,7 @@ def build_factors(blocks, n, m, perm_x, xoff, koff, L, tol, workers=None, log=No
         P_off=P_off,
         U=U_all,
         U_off=U_off,
-        skel_L=np.concatenate([J_prev[i] for i in range(nb)]).astype(np.int64),
+        skel_L=np.concatenate([J_last[i] for i in range(nb)]).astype(np.int64),
         build_stats=np.array([[s["level"], s["seconds"], s["rank_min"], s["rank_max"],
                                s["rank_mean"], s["ident"]] for s in stats]),
     )

@@ -350,3 +350,45 @@ def test_arity_other_than_two_or_four_is_rejected(good):
     bad4 = dict(good, arity=np.int64(4))
     with pytest.raises(ValueError):
         B.bfmht_plan_create(bad4, B.F32, 1)
+
+
+def test_factor_calls_check_their_metadata_before_any_device_work():
+    """The device-factorization calls reject bad host metadata with EINVAL and
+    touch no device memory doing so (fake device addresses, no GPU needed)."""
+    fake = ctypes.c_void_p(1 << 20)
+    assert B.bfmht_factor_meta_bytes(-1, 0) == -1
+    assert B.bfmht_factor_meta_bytes(0, 0) == 256
+    assert B.bfmht_factor_meta_bytes(2, 10) % 256 == 0
+    rows, col_off, a_off = [5, 3], [0, 2, 4], [0, 10]
+
+    def cid(rows=rows, col_off=col_off, a_off=a_off, a_len=19, tol=1e-8):
+        B.bfmht_column_id(rows, col_off, a_off, fake, a_len, tol, fake, fake, fake, 1 << 20)
+
+    for kw, msg in [(dict(tol=-1.0), "tol"), (dict(col_off=[1, 2, 4]), "col_off"), (dict(col_off=[0, 3, 2]), "decreases"),
+                    (dict(a_len=15), "outside a"), (dict(rows=[-1, 3]), "row count")]:
+        with pytest.raises(B.BfmhtError, match=msg) as e:
+            cid(**kw)
+        assert e.value.status == B.EINVAL
+    with pytest.raises(ValueError):
+        cid(col_off=[0, 2])                      # binding: wrong length
+    B.bfmht_column_id([], [0], [], None, 0, 1e-8, None, None, None, 0)   # count 0: no-op
+
+    def form(ta=(0, 1, 2, 0), row0=(0, 4), ld=8, w0=3):
+        B.bfmht_form_blocks(list(row0), rows, col_off, list(ta), [0, 0, 0, 0], a_off, fake, ld, w0, fake, ld, 1,
+                            fake, 19, fake, 1 << 20)
+
+    with pytest.raises(B.BfmhtError, match="table column") as e:
+        form(ta=(0, 1, 3, 0))
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.BfmhtError, match="outside the tables"):
+        form(row0=(0, 6))
+    with pytest.raises(B.BfmhtError, match="negative"):
+        form(ld=-1)
+
+    def coef(rank=(1, 2), p_off=(0, 2), p_len=6):
+        B.bfmht_id_coefficients(rows, col_off, a_off, fake, 19, list(rank), fake, list(p_off), fake, p_len, fake, 1 << 20)
+
+    with pytest.raises(B.BfmhtError, match="bad rank"):
+        coef(rank=(3, 1))
+    with pytest.raises(B.BfmhtError, match="outside p"):
+        coef(p_len=5)
