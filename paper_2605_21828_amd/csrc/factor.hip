@@ -38,7 +38,7 @@
 
 namespace {
 
-constexpr int kIdThreads = 512;       // 8 waves per block
+constexpr int kIdThreads = 512;       // 8 waves per block (4 for the largest register cache)
 constexpr int kIdWaves = kIdThreads / 64;
 constexpr int kFormThreads = 256;
 constexpr int kCoefThreads = 256;
@@ -69,11 +69,18 @@ __device__ __forceinline__ int block_of(const int64_t *col_off, int count, int64
   return lo;
 }
 
-// Staged metadata: per block row0, rows, col_off (count + 1), a_off; per column ta, tb.
+// Staged metadata: per block row0, rows, col_off (count + 1), a_off, prow; per
+// column ta, tb.  prow: the rows the pivoted QR works on, rows itself, or K for
+// a tall block (rows > 4 K) that is first reduced to its triangular factor.
 struct Meta {
-  const int64_t *row0, *rows, *col_off, *a_off;
+  const int64_t *row0, *rows, *col_off, *a_off, *prow;
   const int32_t *ta, *tb;
 };
+
+// A block more than four times taller than wide is first reduced to R by an unpivoted
+// blocked QR; pivoting then runs on the K x K triangle (the same pivots and R
+// in exact arithmetic, since pivoting reads only column norms of Q^T A).
+__host__ __device__ inline bool reduce_first(int64_t M, int64_t K) { return K > 0 && M > 4 * K; }
 
 __global__ __launch_bounds__(kFormThreads) void form_blocks_kernel(Meta md, int count, const double *__restrict__ tab0,
                                                                    int64_t ld0, const double *__restrict__ tab1,
@@ -88,6 +95,252 @@ __global__ __launch_bounds__(kFormThreads) void form_blocks_kernel(Meta md, int 
   for (int64_t i = threadIdx.x; i < M; i += kFormThreads) out[i] = t0[i] * t1[i];
 }
 
+// Unpivoted blocked Householder QR of the tall blocks (reduce_first), in
+// place: R in the upper triangle of the top K rows, cleared below the diagonal
+// at the end so the pivoted QR sees R.  Panels of kPanel columns, one launch
+// pair per panel position over all blocks:
+//   hqr_panel_kernel   one workgroup per block factors the panel left-looking:
+//                      column p0 + j first takes the panel's earlier reflectors
+//                      in compact form H_0 ... H_{j-1} = I - V T V^T (T upper
+//                      triangular, extended by the forward recurrence
+//                      T(0:j, j) = -tau_j T(0:j, 0:j) V^T v_j), then yields
+//                      reflector j; T goes to the block's slot in tbuf;
+//   hqr_trail_kernel   a grid over (block, group of columns) applies
+//                      Q^T = I - V T^T V^T to every column right of the panel in
+//                      two passes over its rows, a wave per column.
+// Trailing columns are thus streamed once per panel, not once per column, and
+// the trailing update has many workgroups per block to hide memory latency.
+constexpr int kPanel = 16;
+constexpr int kPanelThreads = 512;
+constexpr int kTrailThreads = 256;
+constexpr int kTrailCols = 16;          // columns per trailing workgroup (4 per wave)
+constexpr int kRowsInFlight = 2;        // rows per lane whose loads are issued together
+
+// Sums over the workgroup of vals[t], t < n (n <= kPanel); every thread gets them.
+template <int NW>
+__device__ __forceinline__ void block_sums(double *vals, int n, double (*slots)[kPanel], int lane, int wave) {
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t)
+    if (t < n) {
+      const double v = wave_sum(vals[t]);
+      if (lane == 0) slots[wave][t] = v;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kPanel; ++t)
+    if (t < n) {
+      double v = 0.0;
+      for (int w = 0; w < NW; ++w) v += slots[w][t];
+      vals[t] = v;
+    }
+  __syncthreads();
+}
+
+// V(i, t) of the panel starting at column p0: 1 at i = p0 + t, 0 above, the
+// stored reflector below.  i < M: the load is issued unconditionally (and the
+// value selected), so the loads of a row do not wait on each other.
+__device__ __forceinline__ double vpanel(const double *A, int64_t M, int p0, int t, int64_t i) {
+  const int64_t d = i - (p0 + t);
+  const double raw = A[(int64_t)(p0 + t) * M + i];
+  return d > 0 ? raw : (d == 0 ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(kPanelThreads) void hqr_panel_kernel(Meta md, int p0, double *__restrict__ a,
+                                                                  double *__restrict__ tbuf) {
+  constexpr int NW = kPanelThreads / 64;
+  constexpr int U = kRowsInFlight;
+  __shared__ double T[kPanel][kPanel];
+  __shared__ double slots[NW][kPanel];
+  const int b = blockIdx.x;
+  const int64_t M = md.rows[b];
+  const int K = (int)(md.col_off[b + 1] - md.col_off[b]);
+  if (!reduce_first(M, K) || p0 >= K) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *A = a + md.a_off[b];
+  const int pw = std::min(kPanel, K - p0);
+  for (int jj = 0; jj < pw; ++jj) {
+    const int c = p0 + jj;
+    double *col = A + (int64_t)c * M;
+    double v[kPanel];
+    if (jj > 0) {
+      // the panel's earlier reflectors: w = V^T a, a -= V (T^T w)
+#pragma unroll
+      for (int t = 0; t < kPanel; ++t) v[t] = 0.0;
+      // (entries t >= jj are formed too and discarded, so no branch separates the
+      // loads; no column past the panel's last, p0 + pw - 1, is addressed)
+      for (int64_t i0 = p0 + tid; i0 < M; i0 += (int64_t)kPanelThreads * U) {
+        double x[U];
+        int64_t iu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = i0 + (int64_t)kPanelThreads * u;
+          iu[u] = i < M ? i : M - 1;
+          x[u] = i < M ? col[iu[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < kPanel; ++t) v[t] = fma(vpanel(A, M, p0, t < pw ? t : pw - 1, iu[u]), x[u], v[t]);
+      }
+      block_sums<NW>(v, jj, slots, lane, wave);
+      double y[kPanel];
+#pragma unroll
+      for (int t = 0; t < kPanel; ++t) {
+        double s0 = 0.0;
+        for (int r = 0; r <= t && r < jj; ++r) s0 = fma(T[r][t], v[r], s0);
+        y[t] = t < jj ? s0 : 0.0;
+      }
+      for (int64_t i = p0 + tid; i < M; i += kPanelThreads) {
+        double d0 = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPanel; ++t) d0 = fma(vpanel(A, M, p0, t < pw ? t : pw - 1, i), y[t], d0);   // y[t] = 0, t >= jj
+        col[i] -= d0;
+      }
+      __syncthreads();
+    }
+    // reflector of column c over rows c..M-1
+    const double alpha = col[c];
+    v[0] = 0.0;
+    for (int64_t i0 = c + 1 + tid; i0 < M; i0 += (int64_t)kPanelThreads * U) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)kPanelThreads * u;
+        x[u] = i < M ? col[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[0] = fma(x[u], x[u], v[0]);
+    }
+    block_sums<NW>(v, 1, slots, lane, wave);
+    const double s = v[0];
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (s > 0.0) {
+      beta = -std::copysign(std::sqrt(alpha * alpha + s), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    for (int64_t i = c + 1 + tid; i < M; i += kPanelThreads) col[i] *= scal;
+    __syncthreads();   // the reflector is stored; row c still holds alpha
+    // T column jj: z = V(:, 0:jj)^T v_jj, T(0:jj, jj) = -tau T(0:jj, 0:jj) z
+    if (jj > 0) {
+#pragma unroll
+      for (int t = 0; t < kPanel; ++t) v[t] = 0.0;
+      for (int64_t i0 = c + tid; i0 < M; i0 += (int64_t)kPanelThreads * U) {
+        double x[U];
+        int64_t iu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t i = i0 + (int64_t)kPanelThreads * u;
+          iu[u] = i < M ? i : M - 1;
+          x[u] = i < M ? (i == c ? 1.0 : col[iu[u]]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < kPanel; ++t) v[t] = fma(vpanel(A, M, p0, t < pw ? t : pw - 1, iu[u]), x[u], v[t]);
+      }
+      block_sums<NW>(v, jj, slots, lane, wave);
+    }
+    if (tid == 0) {
+      for (int r = 0; r < jj; ++r) {
+        double acc = 0.0;
+        for (int t = r; t < jj; ++t) acc += T[r][t] * v[t];
+        T[r][jj] = -tau * acc;
+      }
+      T[jj][jj] = tau;
+      for (int r = jj + 1; r < kPanel; ++r) T[r][jj] = 0.0;
+      col[c] = beta;
+    }
+    __syncthreads();
+  }
+  double *tb = tbuf + (int64_t)b * kPanel * kPanel;
+  for (int e = tid; e < kPanel * kPanel; e += kPanelThreads) {
+    const int r = e / kPanel, t = e % kPanel;
+    tb[e] = (r < pw && t < pw) ? T[r][t] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kTrailThreads) void hqr_trail_kernel(Meta md, int p0, double *__restrict__ a,
+                                                                  const double *__restrict__ tbuf) {
+  constexpr int NW = kTrailThreads / 64;
+  constexpr int U = kRowsInFlight;
+  __shared__ double T[kPanel][kPanel];
+  const int b = blockIdx.x;
+  const int64_t M = md.rows[b];
+  const int K = (int)(md.col_off[b + 1] - md.col_off[b]);
+  if (!reduce_first(M, K) || p0 >= K) return;
+  // a panel with columns to its right is a full one: kPanel reflectors
+  const int first = p0 + kPanel + blockIdx.y * kTrailCols;
+  if (first >= K) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double *tb = tbuf + (int64_t)b * kPanel * kPanel;
+  for (int e = tid; e < kPanel * kPanel; e += kTrailThreads) T[e / kPanel][e % kPanel] = tb[e];
+  __syncthreads();
+  double *A = a + md.a_off[b];
+  const int last = std::min(K, first + kTrailCols);
+  for (int cc = first + wave; cc < last; cc += NW) {
+    double *x = A + (int64_t)cc * M;
+    double w[kPanel];
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) w[t] = 0.0;
+    for (int64_t i0 = p0 + lane; i0 < M; i0 += 64 * U) {
+      double xa[U];
+      int64_t iu[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u;
+        iu[u] = i < M ? i : M - 1;
+        xa[u] = i < M ? x[iu[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < kPanel; ++t) w[t] = fma(vpanel(A, M, p0, t, iu[u]), xa[u], w[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) w[t] = wave_sum(w[t]);
+    // w <- T^T w: lane t < kPanel forms entry t from column t of T, then every
+    // lane takes the entries back by shuffles
+    {
+      const int tl = lane & (kPanel - 1);
+      double yt = 0.0;
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r) yt = fma(r <= tl ? T[r][tl] : 0.0, w[r], yt);
+#pragma unroll
+      for (int t = 0; t < kPanel; ++t) w[t] = __shfl(yt, t, 64);
+    }
+    for (int64_t i0 = p0 + lane; i0 < M; i0 += 64 * U) {
+      double d[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u;
+        const int64_t ic = i < M ? i : M - 1;
+        d[u] = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPanel; ++t) d[u] = fma(vpanel(A, M, p0, t, ic), w[t], d[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + 64 * u;
+        if (i < M) x[i] -= d[u];
+      }
+    }
+  }
+}
+
+// Clear below the diagonal of the top K rows of every reduced block.
+__global__ __launch_bounds__(256) void hqr_clear_kernel(Meta md, double *__restrict__ a) {
+  const int b = blockIdx.x;
+  const int64_t M = md.rows[b];
+  const int K = (int)(md.col_off[b + 1] - md.col_off[b]);
+  if (!reduce_first(M, K)) return;
+  double *A = a + md.a_off[b];
+  for (int64_t e = threadIdx.x; e < (int64_t)K * K; e += 256) {
+    const int c = (int)(e / K), i = (int)(e % K);
+    if (i > c) A[(int64_t)c * M + i] = 0.0;
+  }
+}
+
 // Column-pivoted QR of one block per workgroup, in place.  LDS: the column
 // sums of squares (K doubles), the logical-to-stored column map (K ints), the
 // reflector below the diagonal (up to vcap doubles; beyond that it is read back
@@ -95,26 +348,28 @@ __global__ __launch_bounds__(kFormThreads) void form_blocks_kernel(Meta md, int 
 // 64 R + 1 rows and its whole reflector fits vcap, so a wave keeps the column
 // it updates in R registers per lane (one read and one write per step);
 // R = 0: the column is read twice per step.
-template <int R>
-__global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int vcap, double *__restrict__ a, double tol,
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void cpqr_kernel(Meta md, int kmax, int vcap, double *__restrict__ a, double tol,
                                                           int32_t *__restrict__ rank_out, int32_t *__restrict__ piv_out) {
+  constexpr int NW = NT / 64;
   extern __shared__ double lds[];
   double *nrm = lds;                                        // [kmax]
   double *vl = nrm + kmax;                                  // [vcap]
-  double *red = vl + vcap;                                  // [2 * kIdWaves]
-  int *redi = reinterpret_cast<int *>(red + 2 * kIdWaves);  // [kIdWaves]
-  int *colmap = redi + kIdWaves;                            // [kmax]
+  double *red = vl + vcap;                                  // [2 * NW]
+  int *redi = reinterpret_cast<int *>(red + 2 * NW);  // [NW]
+  int *colmap = redi + NW;                            // [kmax]
 
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t M = md.rows[b];
+  const int64_t M = md.prow[b];    // rows of the matrix pivoted on (the triangle of a reduced block)
+  const int64_t ld = md.rows[b];
   const int64_t c0 = md.col_off[b];
   const int K = (int)(md.col_off[b + 1] - c0);
   double *A = a + md.a_off[b];
 
-  for (int c = tid; c < K; c += kIdThreads) colmap[c] = c;
-  for (int c = wave; c < K; c += kIdWaves) {
-    const double *col = A + (int64_t)c * M;
+  for (int c = tid; c < K; c += NT) colmap[c] = c;
+  for (int c = wave; c < K; c += NW) {
+    const double *col = A + (int64_t)c * ld;
     double s = 0.0;
     for (int64_t i = lane; i < M; i += 64) s = fma(col[i], col[i], s);
     s = wave_sum(s);
@@ -129,7 +384,7 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
     // pivot: the largest remaining sum of squares, first index on ties
     double bv = -1.0;
     int bi = K;
-    for (int c = j + tid; c < K; c += kIdThreads) better(bv, bi, nrm[c], c);
+    for (int c = j + tid; c < K; c += NT) better(bv, bi, nrm[c], c);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) better(bv, bi, __shfl_xor(bv, o, 64), __shfl_xor(bi, o, 64));
     if (lane == 0) {
@@ -139,7 +394,7 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
     __syncthreads();
     bv = red[0];
     bi = redi[0];
-    for (int w = 1; w < kIdWaves; ++w) better(bv, bi, red[w], redi[w]);
+    for (int w = 1; w < NW; ++w) better(bv, bi, red[w], redi[w]);
     const double pn = std::sqrt(bv);
     if (j == 0) d0 = pn;
     if (!(pn > tol * d0) || d0 == 0.0) {   // uniform over the workgroup
@@ -158,15 +413,15 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
     __syncthreads();
 
     // reflector of the pivot column, rows j..M-1
-    double *pcol = A + (int64_t)colmap[j] * M;
+    double *pcol = A + (int64_t)colmap[j] * ld;
     const double alpha = pcol[j];
     double s = 0.0;
-    for (int64_t i = j + 1 + tid; i < M; i += kIdThreads) s = fma(pcol[i], pcol[i], s);
+    for (int64_t i = j + 1 + tid; i < M; i += NT) s = fma(pcol[i], pcol[i], s);
     s = wave_sum(s);
-    if (lane == 0) red[kIdWaves + wave] = s;
+    if (lane == 0) red[NW + wave] = s;
     __syncthreads();
     s = 0.0;
-    for (int w = 0; w < kIdWaves; ++w) s += red[kIdWaves + w];
+    for (int w = 0; w < NW; ++w) s += red[NW + w];
     double tau = 0.0, beta = alpha, scal = 0.0;
     if (s > 0.0) {
       beta = -std::copysign(std::sqrt(alpha * alpha + s), alpha);
@@ -174,7 +429,7 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
       scal = 1.0 / (alpha - beta);
     }
     const int64_t nv = M - j - 1;
-    for (int64_t i = tid; i < nv; i += kIdThreads) {
+    for (int64_t i = tid; i < nv; i += NT) {
       const double v = pcol[j + 1 + i] * scal;
       pcol[j + 1 + i] = v;
       if (i < vcap) vl[i] = v;
@@ -183,8 +438,8 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
     if (tid == 0) pcol[j] = beta;
 
     // apply H to every remaining column and recompute its sum of squares below row j
-    for (int c = j + 1 + wave; c < K; c += kIdWaves) {
-      double *col = A + (int64_t)colmap[c] * M;
+    for (int c = j + 1 + wave; c < K; c += NW) {
+      double *col = A + (int64_t)colmap[c] * ld;
       double *cb = col + j + 1;
       double w = 0.0, s2 = 0.0;
       if constexpr (R > 0) {
@@ -241,7 +496,7 @@ __global__ __launch_bounds__(kIdThreads) void cpqr_kernel(Meta md, int kmax, int
     __syncthreads();
   }
   if (tid == 0) rank_out[b] = k;
-  for (int c = tid; c < K; c += kIdThreads) piv_out[c0 + c] = colmap[c];
+  for (int c = tid; c < K; c += NT) piv_out[c0 + c] = colmap[c];
 }
 
 // P of one block (row-major k x K at p + p_off): positions s < k of the pivot
@@ -342,14 +597,16 @@ bfmht_status check_blocks(const char *who, int32_t count, const int64_t *row0, c
 }
 
 // Layout of the metadata workspace: per block row0, rows, col_off (count + 1),
-// a_off (int64); then p_off (int64) and rank (int32) per block; then the
-// per-column table rows ta, tb (int32).
+// a_off, prow (int64); then p_off (int64) and rank (int32) per block; the
+// blocked QR's panel T (kPanel^2 doubles) per block; then the per-column table
+// rows ta, tb (int32).
 struct MetaLayout {
-  int64_t poff, rank, ta, tb, total;
+  int64_t poff, rank, tq, ta, tb, total;
   MetaLayout(int64_t count, int64_t tc) {
-    poff = round256((4 * count + 1) * 8);
+    poff = round256((5 * count + 1) * 8);
     rank = poff + round256(count * 8);
-    ta = rank + round256(count * 4);
+    tq = rank + round256(count * 4);                       // per block: T of the current panel
+    ta = tq + round256(count * kPanel * kPanel * 8);
     tb = ta + round256(tc * 4);
     total = tb + round256(tc * 4);
   }
@@ -367,11 +624,13 @@ bfmht_status stage_meta(const char *who, int32_t count, const int64_t *row0, con
   if (!ws || ws_bytes < need)
     return bfmht::set_error(BFMHT_ENOSPACE, std::string(who) + ": metadata workspace smaller than " +
                                                 std::to_string(need) + " bytes");
-  std::vector<int64_t> h(4 * (size_t)count + 1, 0);
+  std::vector<int64_t> h(5 * (size_t)count + 1, 0);
   for (int32_t b = 0; b < count; ++b) {
+    const int64_t K = col_off[b + 1] - col_off[b];
     h[b] = row0 ? row0[b] : 0;
     h[count + b] = rows[b];
     h[3 * (size_t)count + 1 + b] = a_off[b];
+    h[4 * (size_t)count + 1 + b] = reduce_first(rows[b], K) ? K : rows[b];
   }
   for (int32_t b = 0; b <= count; ++b) h[2 * (size_t)count + b] = col_off[b];
   char *base = static_cast<char *>(ws);
@@ -381,6 +640,7 @@ bfmht_status stage_meta(const char *who, int32_t count, const int64_t *row0, con
   md->rows = d + count;
   md->col_off = d + 2 * (size_t)count;
   md->a_off = d + 3 * (size_t)count + 1;
+  md->prow = d + 4 * (size_t)count + 1;
   md->ta = reinterpret_cast<const int32_t *>(base + lay.ta);
   md->tb = reinterpret_cast<const int32_t *>(base + lay.tb);
   if (e == hipSuccess && p_off) e = hipMemcpyAsync(base + lay.poff, p_off, (size_t)count * 8, hipMemcpyHostToDevice, st);
@@ -444,28 +704,62 @@ extern "C" bfmht_status bfmht_column_id(int32_t count, const int64_t *rows, cons
   if (fixed > lds_max)
     return bfmht::set_error(BFMHT_EINVAL, std::string(who) + ": " + std::to_string(kmax) +
                                               " columns in one block exceed the workgroup's local memory");
-  const int64_t vcap = std::min<int64_t>(mmax, (lds_max - fixed) / 8);
+  // rows the pivoted QR works on: K for blocks reduced first, else all rows
+  int64_t pmax = 0;
+  bool any_reduce = false;
+  for (int32_t b = 0; b < count; ++b) {
+    const int64_t K = col_off[b + 1] - col_off[b];
+    const bool r = reduce_first(rows[b], K);
+    any_reduce = any_reduce || r;
+    pmax = std::max(pmax, r ? K : rows[b]);
+  }
+  const int64_t vcap = std::min<int64_t>(pmax, (lds_max - fixed) / 8);
   const int64_t lds = (kmax + vcap + 3 * kIdWaves) * 8 + kmax * 4;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Meta md;
   st = stage_meta(who, count, nullptr, rows, col_off, a_off, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, s, &md);
   if (st != BFMHT_OK) return st;
+  if (any_reduce) {
+    double *tq = reinterpret_cast<double *>(static_cast<char *>(ws) + MetaLayout(count, col_off[count]).tq);
+    int64_t kred = 0;   // widest reduced block
+    for (int32_t b = 0; b < count; ++b) {
+      const int64_t K = col_off[b + 1] - col_off[b];
+      if (reduce_first(rows[b], K)) kred = std::max(kred, K);
+    }
+    hipError_t e0 = hipSuccess;
+    for (int p0 = 0; p0 < kred && e0 == hipSuccess; p0 += kPanel) {
+      hipLaunchKernelGGL(hqr_panel_kernel, dim3((unsigned)count), dim3(kPanelThreads), 0, s, md, p0, a, tq);
+      const int64_t ntrail = kred - p0 - kPanel;
+      if (ntrail > 0) {
+        const dim3 grid((unsigned)count, (unsigned)((ntrail + kTrailCols - 1) / kTrailCols));
+        hipLaunchKernelGGL(hqr_trail_kernel, grid, dim3(kTrailThreads), 0, s, md, p0, a, (const double *)tq);
+      }
+      e0 = hipGetLastError();
+    }
+    if (e0 == hipSuccess) {
+      hipLaunchKernelGGL(hqr_clear_kernel, dim3((unsigned)count), dim3(256), 0, s, md, a);
+      e0 = hipGetLastError();
+    }
+    if (e0 != hipSuccess) return bfmht::set_error(BFMHT_EHIP, std::string(who) + ": " + hipGetErrorString(e0));
+  }
   // registers per lane for the cached column: the smallest R with 64 R >= the longest reflector
-  const int64_t nvmax = std::max<int64_t>(mmax - 1, 0);
-  const int R = nvmax > vcap ? 0 : nvmax <= 256 ? 4 : nvmax <= 1024 ? 16 : nvmax <= 2048 ? 32 : 0;
-  const void *fn = R == 4    ? reinterpret_cast<const void *>(cpqr_kernel<4>)
-                   : R == 16 ? reinterpret_cast<const void *>(cpqr_kernel<16>)
-                   : R == 32 ? reinterpret_cast<const void *>(cpqr_kernel<32>)
-                             : reinterpret_cast<const void *>(cpqr_kernel<0>);
+  const int64_t nvmax = std::max<int64_t>(pmax - 1, 0);
+  const int R = nvmax > vcap ? 0 : nvmax <= 256 ? 4 : nvmax <= 1024 ? 16 : nvmax <= 2048 ? 32 : nvmax <= 4096 ? 64 : 0;
+  const void *fn = R == 4    ? reinterpret_cast<const void *>(cpqr_kernel<4, 512>)
+                   : R == 16 ? reinterpret_cast<const void *>(cpqr_kernel<16, 512>)
+                   : R == 32 ? reinterpret_cast<const void *>(cpqr_kernel<32, 512>)
+                   : R == 64 ? reinterpret_cast<const void *>(cpqr_kernel<64, 256>)
+                             : reinterpret_cast<const void *>(cpqr_kernel<0, 512>);
   hipError_t e = hipSuccess;
   if (lds > 65536) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess) {
-    const dim3 grid((unsigned)count), block(kIdThreads);
+    const dim3 grid((unsigned)count), block(512), block4(256);
     const int ik = (int)kmax, iv = (int)vcap;
-    if (R == 4) hipLaunchKernelGGL(cpqr_kernel<4>, grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
-    else if (R == 16) hipLaunchKernelGGL(cpqr_kernel<16>, grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
-    else if (R == 32) hipLaunchKernelGGL(cpqr_kernel<32>, grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
-    else hipLaunchKernelGGL(cpqr_kernel<0>, grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
+    if (R == 4) hipLaunchKernelGGL((cpqr_kernel<4, 512>), grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
+    else if (R == 16) hipLaunchKernelGGL((cpqr_kernel<16, 512>), grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
+    else if (R == 32) hipLaunchKernelGGL((cpqr_kernel<32, 512>), grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
+    else if (R == 64) hipLaunchKernelGGL((cpqr_kernel<64, 256>), grid, block4, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
+    else hipLaunchKernelGGL((cpqr_kernel<0, 512>), grid, block, (size_t)lds, s, md, ik, iv, a, tol, rank, piv);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return bfmht::set_error(BFMHT_EHIP, std::string(who) + ": " + hipGetErrorString(e));

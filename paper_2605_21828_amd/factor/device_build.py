@@ -24,7 +24,6 @@ import numpy as np
 import torch
 
 from .. import bfmht as B
-from .build import pack_factor_set
 
 
 class Tables:
@@ -103,8 +102,11 @@ class _Runner:
                             t.tab1.data_ptr(), t.n, t.w1, a.data_ptr(), a_len, ws.data_ptr(), ws_bytes, self.stream)
         return dict(rows=np.asarray(rows, np.int64), col_off=col_off, a_off=a_off, a_len=a_len, K=K)
 
-    def column_ids(self, lay, tol):
-        """Column IDs of the formed blocks: per block (local J, P or None, ident)."""
+    def column_ids_device(self, lay, tol):
+        """Column IDs of the formed blocks, P left on the device: returns
+        (rank, piv, p_off, p) with rank and piv on the host, p_off[b] the offset of
+        block b's P in the device tensor p (-1 when the block keeps all or none
+        of its columns; p is None when no block has a P)."""
         count = len(lay["rows"])
         tc = int(lay["col_off"][-1])
         rank_d = torch.empty(max(count, 1), dtype=torch.int32, device=self.dev)
@@ -128,16 +130,21 @@ class _Runner:
         sz = np.where(need, rank.astype(np.int64) * K, 0)
         p_off[need] = np.concatenate([[0], np.cumsum(sz)[:-1]])[need]
         p_len = int(sz.sum())
-        P_h = None
+        p_d = None
         if p_len:
             p_d = torch.empty(p_len, dtype=torch.float64, device=self.dev)
             B.bfmht_id_coefficients(lay["rows"], lay["col_off"], lay["a_off"], self.a.data_ptr(), lay["a_len"], rank,
                                     piv_d.data_ptr(), p_off, p_d.data_ptr(), p_len, ws.data_ptr(), ws_bytes,
                                     self.stream)
-            P_h = p_d.cpu().numpy()
+        return rank, piv, p_off, p_d
+
+    def column_ids(self, lay, tol):
+        """Column IDs of the formed blocks: per block (local J, P or None, ident) on the host."""
+        rank, piv, p_off, p_d = self.column_ids_device(lay, tol)
+        P_h = p_d.cpu().numpy() if p_d is not None else None
         out = []
-        for b in range(count):
-            k, Kb, c0 = int(rank[b]), int(K[b]), int(lay["col_off"][b])
+        for b in range(len(rank)):
+            k, Kb, c0 = int(rank[b]), int(lay["K"][b]), int(lay["col_off"][b])
             if k == Kb:
                 out.append((np.arange(Kb, dtype=np.int64), None, True))
             elif k == 0:
@@ -190,7 +197,9 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
         raise ValueError("tables cover %d points, the factor set %d" % (tables.n, n))
     rank = np.zeros((L + 1, nb), dtype=np.int32)
     ident = np.zeros((L + 1, nb), dtype=np.uint8)
-    P_blocks = [[None] * nb for _ in range(L + 1)]
+    P_off = np.full((L + 1, nb), -1, dtype=np.int64)
+    p_parts = []     # device P of every chunk, in level-major block order
+    p_total = 0
     J_prev = None
     stats = []
     budget_el = max(1, int(budget_bytes) // 8)
@@ -215,18 +224,32 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
             if cols.size == 0:
                 J_cur[q], rank[lvl, q], ident[lvl, q] = cols, 0, 1
             elif M == 0:
-                J_cur[q], rank[lvl, q], P_blocks[lvl][q] = cols[:0], 0, np.zeros((0, cols.size))
+                J_cur[q], rank[lvl, q] = cols[:0], 0
             else:
                 dev_tasks.append((q, r0, M, cols))
         sizes = [M * cols.size for _, _, M, cols in dev_tasks]
         for s0, s1 in _chunks(sizes, budget_el):
             part = dev_tasks[s0:s1]
             lay = run.form([t[1] for t in part], [t[2] for t in part], [t[3] for t in part])
-            for (q, _, _, cols), (J, P, idf) in zip(part, run.column_ids(lay, tol)):
-                J_cur[q] = cols[J]
-                rank[lvl, q] = len(J)
-                ident[lvl, q] = 1 if idf else 0
-                P_blocks[lvl][q] = P
+            rk, piv, p_off, p_d = run.column_ids_device(lay, tol)
+            for b, (q, _, _, cols) in enumerate(part):
+                k, Kb, c0 = int(rk[b]), cols.size, int(lay["col_off"][b])
+                rank[lvl, q] = k
+                if k == Kb:
+                    ident[lvl, q] = 1
+                    J_cur[q] = cols
+                else:
+                    J_cur[q] = cols[piv[c0:c0 + k]]
+                    if k > 0:
+                        P_off[lvl, q] = p_total + p_off[b]
+            if p_d is not None:
+                p_parts.append(p_d)
+                p_total += p_d.numel()
+        # blocks that keep no column have an empty P at the running offset
+        for q in range(nb):
+            if not ident[lvl, q] and rank[lvl, q] == 0:
+                later = P_off[lvl, q + 1:][P_off[lvl, q + 1:] >= 0]
+                P_off[lvl, q] = later[0] if later.size else p_total
         J_prev = J_cur
         st = dict(level=lvl, seconds=round(time.time() - t0, 3),
                   rank_min=int(rank[lvl].min()), rank_max=int(rank[lvl].max()),
@@ -234,8 +257,12 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
         stats.append(st)
         if log:
             log(st)
+    P_all = torch.cat(p_parts).cpu().numpy() if p_parts else np.zeros(0)
+    del p_parts
     # leaf column bases U_i = Phi(tau_i, J_{L,i}), formed on the GPU
-    U_list = [np.zeros((int(xoff[i + 1] - xoff[i]), J_prev[i].size)) for i in range(nb)]
+    U_off = np.zeros(nb, dtype=np.int64)
+    U_off[1:] = np.cumsum([(xoff[i + 1] - xoff[i]) * J_prev[i].size for i in range(nb - 1)])
+    U_all = np.zeros(int(U_off[-1] + (xoff[nb] - xoff[nb - 1]) * J_prev[nb - 1].size))
     leaf = [i for i in range(nb) if xoff[i + 1] > xoff[i] and J_prev[i].size]
     sizes = [int(xoff[i + 1] - xoff[i]) * J_prev[i].size for i in leaf]
     for s0, s1 in _chunks(sizes, budget_el):
@@ -243,5 +270,11 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
         lay = run.form([int(xoff[i]) for i in part], [int(xoff[i + 1] - xoff[i]) for i in part],
                        [J_prev[i] for i in part])
         for i, U in zip(part, run.blocks_to_host(lay)):
-            U_list[i] = U
-    return pack_factor_set(n, m, L, tol, a_, perm_x, xoff, koff, rank, ident, P_blocks, U_list, J_prev, stats)
+            U_all[U_off[i]:U_off[i] + U.size] = U.ravel()
+    return dict(
+        n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol), arity=np.int64(a_),
+        perm_x=perm_x, xoff=xoff, koff=koff, rank=rank, ident=ident, P=P_all, P_off=P_off,
+        U=U_all, U_off=U_off, skel_L=np.concatenate([J_prev[i] for i in range(nb)]).astype(np.int64),
+        build_stats=np.array([[s["level"], s["seconds"], s["rank_min"], s["rank_max"],
+                               s["rank_mean"], s["ident"]] for s in stats]),
+    )

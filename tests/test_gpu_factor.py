@@ -72,6 +72,8 @@ def _blocks(seed):
     for _ in range(20):                           # ragged random
         M, K = int(rng.integers(1, 400)), int(rng.integers(1, 150))
         out.append(spectrum(M, K, 10.0 ** -rng.uniform(2, 15)))
+    out.append(spectrum(900, 45, 1e-10))          # a tall reduced block whose last panel is partial ...
+    out.append(spectrum(200, 3, 1e-3))            # ... and one narrower than a panel, last in the buffer
     return out
 
 
