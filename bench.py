@@ -489,7 +489,7 @@ def bench_lsq(args):
         host_memory())
     t0 = time.time()
     fs, _ = fio.fourier_factors(pts, m, w["leaf"], w["tol"], workers=args.workers, cache=args.cache,
-                                log=lambda s: log("  factor", s, host_memory()))
+                                log=lambda s: log("  factor", s, host_memory()), device=_build_device(args))
     t_build = time.time() - t0
     F = fio.stored_entries(fs)
     modes = real_modes(m)
@@ -538,6 +538,9 @@ def bench_lsq(args):
     ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
     ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)
     roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2 - folded_levels(fs))
+    roof["traffic"] = measured_traffic(w_key := "iid" + args.workload[len("lsq"):], "fwd")
+    roof["traffic_unit"] = "bytes per launch"
+    roof["traffic_transposed"] = measured_traffic(w_key, "bwd")
     base, acc = None, {}
     if not args.no_cpu_baseline:
         log("oracle checks: finite differences and dense gradient")
@@ -552,7 +555,8 @@ def bench_lsq(args):
                    "L": int(fs["L"]), "step": "forward apply + autograd backward (transposed apply) + update"},
         "roofline": roof,
         "cpu_baseline": base,
-        "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "host_build_seconds": t_build,
+        "extra": {"stored_factor_entries": F, "compression_vs_dense": n * m / F, "factor_build_seconds": t_build,
+                  "factor_build_on": "gpu" if args.device_build else "host (NumPy/SciPy, %d workers)" % args.workers,
                   "plan_create_upload_seconds": t_plan, "host_memory_at_end": host_memory(),
                   "fp32_apply_ms": ms_fwd, "fp32_apply_transpose_ms": ms_bwd, "step_size": lr,
                   "loss_first": losses[0], "loss_last": losses[-1],
@@ -805,8 +809,10 @@ def bench_build(args):
     events = []
     t0 = time.perf_counter()
     tabs = fourier_tables(pts, modes, perm, dev)
+    torch.cuda.synchronize()
+    t_tab = time.perf_counter() - t0
     fs = build_factors_device(tabs, n, m, perm, xoff, koff, L, tol, events=events,
-                              log=lambda s: log("  level", s))
+                              log=lambda s: log("  build", s))
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     id_ms = sum(a.elapsed_time(b) for a, b in events)
@@ -887,7 +893,8 @@ def bench_build(args):
                              "column-ID launches' event time; level-2 updates stream each block once per step, "
                              "so the launches are bound by that traffic rather than the FMA rate"},
         "cpu_baseline": base,
-        "extra": {"column_id_kernel_ms": id_ms, "qr_flops": flops, "stored_entries": fio.stored_entries(fs),
+        "extra": {"column_id_kernel_ms": id_ms, "tables_seconds": t_tab, "qr_flops": flops,
+                  "stored_entries": fio.stored_entries(fs),
                   "levels": [[s[0], s[1], s[2], s[3], s[4], s[5]] for s in fs["build_stats"].tolist()],
                   "fp64_synthesis_rel_err_256_rows": synth_err, "host_build": host,
                   "oracle_sample_check": sample_check, "host_memory_at_end": host_memory()},
@@ -907,6 +914,15 @@ def bench_copy(args):
     ms = event_time(lambda: dst.copy_(src), 5, torch)
     print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                       "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def _build_device(args):
+    """The GPU that builds the factor sets with --device-build (column IDs on
+    the device), else None (the host builder)."""
+    if not getattr(args, "device_build", False):
+        return None
+    import torch
+    return torch.device("cuda:0")
 
 
 def counter_run(args):
@@ -951,7 +967,7 @@ def counter_run(args):
         else:
             w = wl.WORKLOADS[args.workload]
             fs, _ = fio.fourier_factors(wl.points_for(w), w["m"], w["leaf"], w["tol"], workers=args.workers,
-                                        cache=args.cache, arity=args.arity)
+                                        cache=args.cache, arity=args.arity, device=_build_device(args))
             b = w["nrhs"]
         p = Plan(fs, prec, max_nrhs=b, device=dev)
         if args.cache and not args.no_tune:
@@ -987,6 +1003,8 @@ def main():
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     ap.add_argument("--arity", type=int, default=2, choices=(2, 4),
                     help="tree arity of the nonuniform-square workloads (4: quadtree and 4-ary mode tree)")
+    ap.add_argument("--device-build", action="store_true",
+                    help="build the factor sets of the least-squares and counter workloads on the GPU")
     ap.add_argument("--host-build", action="store_true",
                     help="build_* workloads: also time the host builder on the same inputs")
     ap.add_argument("--counter-applies", type=int, default=0,

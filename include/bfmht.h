@@ -322,7 +322,10 @@ bfmht_status bfmht_form_blocks(int32_t count, const int64_t *row0, const int64_t
  * here A ~ A(:, J) P): column-pivoted Householder QR of each block in place (the
  * block is overwritten by R and the reflectors), pivoting on the largest
  * remaining column norm (first column on ties), stopped at the first pivot
- * whose norm is not above tol times the first pivot's.  Outputs (device):
+ * whose norm is not above tol times the first pivot's.  A block with more than
+ * twice as many rows as columns is first reduced to its K x K triangular factor
+ * by an unpivoted blocked QR, and the pivoting runs on that triangle (the same
+ * pivots and R up to rounding).  Outputs (device):
  * rank[b] = k, the number of columns kept (0 for an all-zero block);
  * piv[col_off[b] + s] = the block column (0 .. K_b-1) at pivot position s, for
  * all K_b positions; J = piv[0 .. k).  EINVAL on tol < 0 or a block wider than

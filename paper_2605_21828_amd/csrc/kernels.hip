@@ -1319,8 +1319,13 @@ __global__ __launch_bounds__(kNT) void batched_stage_kernel(SegPack pack) {
     if (pack.s[mid].item0 <= g) lo = mid; else hi = mid - 1;
   }
   const Segment S = pack.s[lo];  // by value: the selected segment only
+  // the order of stage_kernel: item0 is a multiple of 8, so workgroup g runs on
+  // XCD g % 8 = bin x of the segment's tile list and walks that bin's tiles with
+  // the column tiles of each tile back to back (they share its factor rows in L2)
   const int64_t t = g - S.item0;
-  const int tix = (int)(t % S.a.ntiles), ny = (int)(t / S.a.ntiles);
+  const int64_t sb = t >> 3;
+  const int nyt = (S.a.nrhs + BN - 1) / BN;
+  const int tix = (int)((sb / nyt) * 8 + (t & 7)), ny = (int)(sb % nyt);
   if (S.a.vec && S.a.nrhs % BN == 0) run_tile<P, FWD, BN, FM, true>(S.a, tix, ny, lds);
   else run_tile<P, FWD, BN, FM, false>(S.a, tix, ny, lds);
 }

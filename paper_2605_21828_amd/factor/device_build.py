@@ -19,6 +19,7 @@ Blocks without columns keep nothing (identity of size 0) and blocks without
 rows keep no column, as in the host builder; neither goes to the GPU.
 """
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -198,8 +199,20 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
     rank = np.zeros((L + 1, nb), dtype=np.int32)
     ident = np.zeros((L + 1, nb), dtype=np.uint8)
     P_off = np.full((L + 1, nb), -1, dtype=np.int64)
-    p_parts = []     # device P of every chunk, in level-major block order
+    # P of every chunk goes to the host while later levels compute (a copy stream
+    # driven by one worker thread); the parts are joined into one array at the end
+    copy_stream = torch.cuda.Stream(device=device)
+    copier = ThreadPoolExecutor(1)
+    copies, parts, futs = [], {}, []   # (offset, part index); part index -> host array
     p_total = 0
+
+    def _download(i, p_d, ev):
+        h = np.empty(p_d.numel(), dtype=np.float64)
+        with torch.cuda.stream(copy_stream):
+            copy_stream.wait_event(ev)
+            torch.from_numpy(h).copy_(p_d)
+        parts[i] = h
+
     J_prev = None
     stats = []
     budget_el = max(1, int(budget_bytes) // 8)
@@ -243,7 +256,10 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
                     if k > 0:
                         P_off[lvl, q] = p_total + p_off[b]
             if p_d is not None:
-                p_parts.append(p_d)
+                ev = torch.cuda.Event()
+                ev.record(torch.cuda.current_stream(device))
+                futs.append(copier.submit(_download, len(copies), p_d, ev))
+                copies.append((p_total, len(copies)))
                 p_total += p_d.numel()
         # blocks that keep no column have an empty P at the running offset
         for q in range(nb):
@@ -257,8 +273,22 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
         stats.append(st)
         if log:
             log(st)
-    P_all = torch.cat(p_parts).cpu().numpy() if p_parts else np.zeros(0)
-    del p_parts
+    t0 = time.time()
+    copier.shutdown(wait=True)
+    for f in futs:
+        f.result()   # re-raises a failed download
+    P_all = np.empty(p_total, dtype=np.float64)
+
+    def _place(item):
+        off, i = item
+        h = parts.pop(i)
+        P_all[off:off + h.size] = h
+
+    with ThreadPoolExecutor(16) as pool:
+        list(pool.map(_place, copies))
+    if log:
+        log(dict(p_download_wait_seconds=round(time.time() - t0, 3), p_entries=int(P_all.size)))
+    t0 = time.time()
     # leaf column bases U_i = Phi(tau_i, J_{L,i}), formed on the GPU
     U_off = np.zeros(nb, dtype=np.int64)
     U_off[1:] = np.cumsum([(xoff[i + 1] - xoff[i]) * J_prev[i].size for i in range(nb - 1)])
@@ -271,6 +301,8 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
                        [J_prev[i] for i in part])
         for i, U in zip(part, run.blocks_to_host(lay)):
             U_all[U_off[i]:U_off[i] + U.size] = U.ravel()
+    if log:
+        log(dict(leaf_bases_seconds=round(time.time() - t0, 3)))
     return dict(
         n=np.int64(n), m=np.int64(m), L=np.int64(L), tol=np.float64(tol), arity=np.int64(a_),
         perm_x=perm_x, xoff=xoff, koff=koff, rank=rank, ident=ident, P=P_all, P_off=P_off,
