@@ -71,16 +71,16 @@ __device__ __forceinline__ int block_of(const int64_t *col_off, int count, int64
 
 // Staged metadata: per block row0, rows, col_off (count + 1), a_off, prow; per
 // column ta, tb.  prow: the rows the pivoted QR works on, rows itself, or K for
-// a tall block (rows > 4 K) that is first reduced to its triangular factor.
+// a tall block (rows > 2 K) that is first reduced to its triangular factor.
 struct Meta {
   const int64_t *row0, *rows, *col_off, *a_off, *prow;
   const int32_t *ta, *tb;
 };
 
-// A block more than four times taller than wide is first reduced to R by an unpivoted
+// A block more than twice as tall as wide is first reduced to R by an unpivoted
 // blocked QR; pivoting then runs on the K x K triangle (the same pivots and R
 // in exact arithmetic, since pivoting reads only column norms of Q^T A).
-__host__ __device__ inline bool reduce_first(int64_t M, int64_t K) { return K > 0 && M > 4 * K; }
+__host__ __device__ inline bool reduce_first(int64_t M, int64_t K) { return K > 0 && M > 2 * K; }
 
 __global__ __launch_bounds__(kFormThreads) void form_blocks_kernel(Meta md, int count, const double *__restrict__ tab0,
                                                                    int64_t ld0, const double *__restrict__ tab1,
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kFormThreads) void form_blocks_kernel(Meta md, int 
 //                      reflector j; T goes to the block's slot in tbuf;
 //   hqr_trail_kernel   a grid over (block, group of columns) applies
 //                      Q^T = I - V T^T V^T to every column right of the panel in
-//                      two passes over its rows, a wave per column.
+//                      two passes over its rows, a wave per four columns.
 // Trailing columns are thus streamed once per panel, not once per column, and
 // the trailing update has many workgroups per block to hide memory latency.
 constexpr int kPanel = 16;
@@ -263,7 +263,6 @@ __global__ __launch_bounds__(kPanelThreads) void hqr_panel_kernel(Meta md, int p
 __global__ __launch_bounds__(kTrailThreads) void hqr_trail_kernel(Meta md, int p0, double *__restrict__ a,
                                                                   const double *__restrict__ tbuf) {
   constexpr int NW = kTrailThreads / 64;
-  constexpr int U = kRowsInFlight;
   __shared__ double T[kPanel][kPanel];
   const int b = blockIdx.x;
   const int64_t M = md.rows[b];
@@ -278,53 +277,60 @@ __global__ __launch_bounds__(kTrailThreads) void hqr_trail_kernel(Meta md, int p
   __syncthreads();
   double *A = a + md.a_off[b];
   const int last = std::min(K, first + kTrailCols);
-  for (int cc = first + wave; cc < last; cc += NW) {
-    double *x = A + (int64_t)cc * M;
-    double w[kPanel];
+  // a wave takes CW adjacent columns at once, so each reflector entry it loads
+  // serves CW columns
+  constexpr int CW = kTrailCols / NW;
+  const int cbase = first + wave * CW;
+  if (cbase >= last) return;
+  double *x[CW];
+  bool live[CW];
 #pragma unroll
-    for (int t = 0; t < kPanel; ++t) w[t] = 0.0;
-    for (int64_t i0 = p0 + lane; i0 < M; i0 += 64 * U) {
-      double xa[U];
-      int64_t iu[U];
+  for (int q = 0; q < CW; ++q) {
+    live[q] = cbase + q < last;
+    x[q] = A + (int64_t)(live[q] ? cbase + q : cbase) * M;
+  }
+  double w[CW][kPanel];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + 64 * u;
-        iu[u] = i < M ? i : M - 1;
-        xa[u] = i < M ? x[iu[u]] : 0.0;
-      }
+  for (int q = 0; q < CW; ++q)
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+    for (int t = 0; t < kPanel; ++t) w[q][t] = 0.0;
+  for (int64_t i = p0 + lane; i < M; i += 64) {
+    double xa[CW];
 #pragma unroll
-        for (int t = 0; t < kPanel; ++t) w[t] = fma(vpanel(A, M, p0, t, iu[u]), xa[u], w[t]);
+    for (int q = 0; q < CW; ++q) xa[q] = x[q][i];
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) {
+      const double v = vpanel(A, M, p0, t, i);
+#pragma unroll
+      for (int q = 0; q < CW; ++q) w[q][t] = fma(v, xa[q], w[q][t]);
     }
+  }
 #pragma unroll
-    for (int t = 0; t < kPanel; ++t) w[t] = wave_sum(w[t]);
+  for (int q = 0; q < CW; ++q) {
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) w[q][t] = wave_sum(w[q][t]);
     // w <- T^T w: lane t < kPanel forms entry t from column t of T, then every
     // lane takes the entries back by shuffles
-    {
-      const int tl = lane & (kPanel - 1);
-      double yt = 0.0;
+    const int tl = lane & (kPanel - 1);
+    double yt = 0.0;
 #pragma unroll
-      for (int r = 0; r < kPanel; ++r) yt = fma(r <= tl ? T[r][tl] : 0.0, w[r], yt);
+    for (int r = 0; r < kPanel; ++r) yt = fma(r <= tl ? T[r][tl] : 0.0, w[q][r], yt);
 #pragma unroll
-      for (int t = 0; t < kPanel; ++t) w[t] = __shfl(yt, t, 64);
+    for (int t = 0; t < kPanel; ++t) w[q][t] = __shfl(yt, t, 64);
+  }
+  for (int64_t i = p0 + lane; i < M; i += 64) {
+    double d[CW];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) d[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < kPanel; ++t) {
+      const double v = vpanel(A, M, p0, t, i);
+#pragma unroll
+      for (int q = 0; q < CW; ++q) d[q] = fma(v, w[q][t], d[q]);
     }
-    for (int64_t i0 = p0 + lane; i0 < M; i0 += 64 * U) {
-      double d[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + 64 * u;
-        const int64_t ic = i < M ? i : M - 1;
-        d[u] = 0.0;
-#pragma unroll
-        for (int t = 0; t < kPanel; ++t) d[u] = fma(vpanel(A, M, p0, t, ic), w[t], d[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + 64 * u;
-        if (i < M) x[i] -= d[u];
-      }
-    }
+    for (int q = 0; q < CW; ++q)
+      if (live[q]) x[q][i] -= d[q];
   }
 }
 
