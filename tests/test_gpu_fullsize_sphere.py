@@ -59,3 +59,22 @@ def test_sphere_full_size_vs_dense(sphere, prec):
         of, og = ob.apply(fs, c[:, cols]), ob.apply_transpose(fs, fv[:, cols])
         assert np.linalg.norm(f[:, cols] - of) <= 1e-12 * np.linalg.norm(of)
         assert np.linalg.norm(g[:, cols] - og) <= 1e-12 * np.linalg.norm(og)
+
+
+def test_sphere_device_factorization_matches_host_build(sphere):
+    """The same factor set built on the GPU (dense eigenvector tables, the same
+    trees): ranks equal to the host build's on (almost) every block, and the FP64
+    synthesis of the GPU-built set within the dense bound."""
+    import torch
+    from paper_2605_21828_amd.bfmht import Plan
+    from paper_2605_21828_amd.factor.device_build import build_factors_device, dense_tables
+    fs, Phi, c, fv, ref_f, ref_g = sphere
+    n, m, L = int(fs["n"]), int(fs["m"]), int(fs["L"])
+    fd = build_factors_device(dense_tables(Phi, fs["perm_x"], torch.device("cuda:0")), n, m, fs["perm_x"],
+                              fs["xoff"], fs["koff"], L, float(fs["tol"]))
+    same = float(np.mean(fd["rank"] == fs["rank"]))
+    print("sphere40962 device build: equal ranks on %.5f of the blocks" % same, flush=True)
+    assert same >= 0.999
+    p = Plan(fd, "f64", max_nrhs=8)
+    f = p.apply(torch.tensor(c[:, :8], dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert od.rel_err_cols(f, ref_f[:, :8])[0] <= TOL["f64"]
