@@ -320,11 +320,12 @@ def bench_batched(args):
         "config": {"workload": "batched32", "instances": [[s, b] for s, b in inst], "m": "n/4",
                    "leaf": spec["leaf"], "tol": spec["tol"], "step": "batched apply + batched apply_transpose"},
         "roofline": {"bound": bound, "achieved": frac * peak, "peak": peak,
-                     "unit": "TFLOP/s" if bound == "mfma" else "GB/s", "frac": frac, "traffic": None,
+                     "unit": "TFLOP/s" if bound == "mfma" else "GB/s", "frac": frac,
+                     "traffic": measured_traffic("batched32", "fwd"), "traffic_unit": "bytes per stage launch",
                      "t_roof_ms": t_roof * 1e3, "t_roof_mfma_bound_ms": t_mfma * 1e3,
                      "t_roof_hbm_bound_ms": t_hbm * 1e3,
                      "note": "sum over instances of max(HBM time, MFMA time); achieved = frac x peak of the "
-                             "dominant bound; traffic: counter bytes of one batched forward call",
+                             "dominant bound; traffic: counter bytes per stage launch of one batched forward call",
                      "traffic_per_batched_apply": measured_traffic("batched32", "fwd", per="apply"),
                      "mfma_busy_pct_counter": measured_mfma_busy("batched32", "fwd"),
                      "kernel": "batched_stage_kernel<1> (all launches of one batched FP32 apply)"},
@@ -742,6 +743,34 @@ def _qr_flops(fs):
     return tot
 
 
+def _id_stream_bytes(fs):
+    """Bytes the column IDs of a factor set must stream at the least: an exactly
+    pivoted step reads every remaining column below the step's row once (it needs
+    every updated norm), 8 (M - j)(K - j) bytes at step j < k; a block with more than
+    twice as many rows as columns pivots on its K x K triangle after a blocked
+    reduction that reads and writes every trailing column once per 16-column panel."""
+    L, nb = int(fs["L"]), 2 ** int(fs["L"])
+    xoff, koff, rank = fs["xoff"], fs["koff"], fs["rank"]
+    tot = 0.0
+    for lvl in range(L + 1):
+        nf = 2 ** (L - lvl)
+        for q in range(nb):
+            i, j = divmod(q, nf)
+            M = int(xoff[(i + 1) * nf] - xoff[i * nf]) if lvl else int(xoff[-1])
+            K = int(koff[j + 1] - koff[j]) if lvl == 0 else int(rank[lvl - 1][(i // 2) * 2 * nf + 2 * j] +
+                                                                 rank[lvl - 1][(i // 2) * 2 * nf + 2 * j + 1])
+            if not (M and K):
+                continue
+            Mp = M
+            if M > 2 * K:
+                p0 = np.arange(0, K, 16, dtype=np.float64)
+                tot += float(np.sum(16.0 * (M - p0) * np.maximum(K - p0 - 16, 0)))
+                Mp = K
+            k = np.arange(int(rank[lvl][q]), dtype=np.float64)
+            tot += float(np.sum(8.0 * (Mp - k) * (K - k)))
+    return tot
+
+
 def _block_skeletons(fs):
     """Per level, per block: (input columns, local skeleton) read back from a
     stored factor set (the unit columns of P; every column of an identity block)."""
@@ -881,19 +910,23 @@ def bench_build(args):
         sample_check = {"blocks": checked, "same_skeleton": agree, "max_rel_P_diff": p_err}
     peak = 78.6   # FP64 vector FMA, TFLOP/s
     tf = flops / (id_ms * 1e-3) / 1e12 if id_ms > 0 else 0.0
+    sbytes = _id_stream_bytes(fs)
+    gbs = sbytes / (id_ms * 1e-3) / 1e9 if id_ms > 0 else 0.0
     res = {
         "metric": "butterfly factorization time on the device (FP64 column IDs)",
         "value": t_dev, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_dev * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "leaf": leaf, "tol": tol, "L": L,
                    "step": "tables, every level's blocks formed and decomposed, leaf bases, factor set packed"},
-        "roofline": {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-                     "traffic": None, "kernel": "cpqr_kernel",
-                     "note": "Householder QR flops (4 (M-j)(K-j) per step, rank steps per block) over the "
-                             "column-ID launches' event time; level-2 updates stream each block once per step, "
-                             "so the launches are bound by that traffic rather than the FMA rate"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                     "traffic": None, "kernel": "hqr_panel/hqr_trail + cpqr_kernel (every bfmht_column_id launch)",
+                     "alg_bytes": sbytes,
+                     "note": "least streamed bytes of exactly pivoted column IDs (one read of the remaining "
+                             "columns per pivot step; tall blocks: their blocked reduction reads and writes each "
+                             "trailing column once per 16-column panel) over the column-ID launches' event time"},
         "cpu_baseline": base,
         "extra": {"column_id_kernel_ms": id_ms, "tables_seconds": t_tab, "qr_flops": flops,
+                  "qr_tflops_fp64": tf, "qr_frac_of_fp64_vector_peak": tf / peak,
                   "stored_entries": fio.stored_entries(fs),
                   "levels": [[s[0], s[1], s[2], s[3], s[4], s[5]] for s in fs["build_stats"].tolist()],
                   "fp64_synthesis_rel_err_256_rows": synth_err, "host_build": host,
