@@ -715,6 +715,7 @@ def bench_latency(args):
         "config": {"workload": "grid64", "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
                    "L": int(fs["L"]), "step": "one apply"},
         "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2 - folded_levels(fs)),
+                         traffic=measured_traffic("grid64", "f64_fwd"), traffic_unit="bytes per launch",
                          note="latency-bound: the factors are L2/MALL-resident; reported, not a target"),
         "cpu_baseline": base,
         "extra": {"stored_factor_entries": F, "precisions": rec, "checks": checks},
@@ -919,7 +920,9 @@ def bench_build(args):
         "config": {"workload": args.workload, "n": n, "m": m, "leaf": leaf, "tol": tol, "L": L,
                    "step": "tables, every level's blocks formed and decomposed, leaf bases, factor set packed"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                     "traffic": None, "kernel": "hqr_panel/hqr_trail + cpqr_kernel (every bfmht_column_id launch)",
+                     "traffic": measured_traffic(args.workload, "id", per="apply"),
+                     "traffic_unit": "bytes per build (every column-ID launch)",
+                     "kernel": "hqr_panel/hqr_trail + cpqr_kernel (every bfmht_column_id launch)",
                      "alg_bytes": sbytes,
                      "note": "least streamed bytes of exactly pivoted column IDs (one read of the remaining "
                              "columns per pivot step; tall blocks: their blocked reduction reads and writes each "
@@ -973,6 +976,21 @@ def counter_run(args):
 
     prec, fwd, count = args.counter_precision, args.counter_direction == "fwd", args.counter_applies
     dev = torch.device("cuda:0")
+    if args.workload.startswith("build_"):
+        # one factorization on the GPU and nothing else (the counters of its column-ID launches)
+        from paper_2605_21828_amd.factor import trees
+        from paper_2605_21828_amd.factor.device_build import build_factors_device, fourier_tables
+        from paper_2605_21828_amd.factor.fourier import real_modes
+        w = wl.WORKLOADS[args.workload[len("build_"):]]
+        pts = wl.points_for(w)
+        L = trees.depth_for(w["n"], w["leaf"])
+        perm, xoff = trees.box_bisection_tree(pts, L)
+        build_factors_device(fourier_tables(pts, real_modes(w["m"]), perm, dev), w["n"], w["m"], perm, xoff,
+                             trees.frequency_tree(w["m"], L), L, w["tol"])
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": args.workload, "precision": "f64", "direction": "build", "applies": 1,
+                          "stage_launches_per_apply": None}), flush=True)
+        return
     dt = torch.float64 if prec == "f64" else torch.float32
     if args.workload == "batched32":
         spec = wl.BATCHED

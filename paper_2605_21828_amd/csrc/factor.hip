@@ -13,7 +13,9 @@
 //                           Phi with a row of ones as the second table);
 //   bfmht_column_id         column-pivoted Householder QR of each block, one
 //                           workgroup per block, stopped at the first pivot
-//                           whose column is shorter than tol |R_00|;
+//                           whose column is shorter than tol |R_00|; a block
+//                           more than twice as tall as wide is first reduced to
+//                           its triangular factor by a blocked QR;
 //   bfmht_id_coefficients   P = [I  R11^-1 R12] Pi^T of each block by back
 //                           substitution, written row-major.
 //
