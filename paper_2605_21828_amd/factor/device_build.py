@@ -216,63 +216,67 @@ def build_factors_device(tables, n, m, perm_x, xoff, koff, L, tol, arity=2, log=
     J_prev = None
     stats = []
     budget_el = max(1, int(budget_bytes) // 8)
-    for lvl in range(L + 1):
-        t0 = time.time()
-        tasks = []   # (q, first row, rows, global columns)
-        if lvl == 0:
-            for j in range(nb):
-                tasks.append((j, 0, n, np.arange(koff[j], koff[j + 1], dtype=np.int64)))
-        else:
-            nf = a_ ** (L - lvl)
-            for i in range(a_ ** lvl):
-                r0, r1 = int(xoff[i * nf]), int(xoff[(i + 1) * nf])
-                p = i // a_
-                for j in range(nf):
-                    q1 = p * (a_ * nf) + a_ * j
-                    cols = np.concatenate([J_prev[q1 + t] for t in range(a_)])
-                    tasks.append((i * nf + j, r0, r1 - r0, cols))
-        J_cur = [None] * nb
-        dev_tasks = []
-        for q, r0, M, cols in tasks:
-            if cols.size == 0:
-                J_cur[q], rank[lvl, q], ident[lvl, q] = cols, 0, 1
-            elif M == 0:
-                J_cur[q], rank[lvl, q] = cols[:0], 0
+    try:
+        for lvl in range(L + 1):
+            t0 = time.time()
+            tasks = []   # (q, first row, rows, global columns)
+            if lvl == 0:
+                for j in range(nb):
+                    tasks.append((j, 0, n, np.arange(koff[j], koff[j + 1], dtype=np.int64)))
             else:
-                dev_tasks.append((q, r0, M, cols))
-        sizes = [M * cols.size for _, _, M, cols in dev_tasks]
-        for s0, s1 in _chunks(sizes, budget_el):
-            part = dev_tasks[s0:s1]
-            lay = run.form([t[1] for t in part], [t[2] for t in part], [t[3] for t in part])
-            rk, piv, p_off, p_d = run.column_ids_device(lay, tol)
-            for b, (q, _, _, cols) in enumerate(part):
-                k, Kb, c0 = int(rk[b]), cols.size, int(lay["col_off"][b])
-                rank[lvl, q] = k
-                if k == Kb:
-                    ident[lvl, q] = 1
-                    J_cur[q] = cols
+                nf = a_ ** (L - lvl)
+                for i in range(a_ ** lvl):
+                    r0, r1 = int(xoff[i * nf]), int(xoff[(i + 1) * nf])
+                    p = i // a_
+                    for j in range(nf):
+                        q1 = p * (a_ * nf) + a_ * j
+                        cols = np.concatenate([J_prev[q1 + t] for t in range(a_)])
+                        tasks.append((i * nf + j, r0, r1 - r0, cols))
+            J_cur = [None] * nb
+            dev_tasks = []
+            for q, r0, M, cols in tasks:
+                if cols.size == 0:
+                    J_cur[q], rank[lvl, q], ident[lvl, q] = cols, 0, 1
+                elif M == 0:
+                    J_cur[q], rank[lvl, q] = cols[:0], 0
                 else:
-                    J_cur[q] = cols[piv[c0:c0 + k]]
-                    if k > 0:
-                        P_off[lvl, q] = p_total + p_off[b]
-            if p_d is not None:
-                ev = torch.cuda.Event()
-                ev.record(torch.cuda.current_stream(device))
-                futs.append(copier.submit(_download, len(copies), p_d, ev))
-                copies.append((p_total, len(copies)))
-                p_total += p_d.numel()
-        # blocks that keep no column have an empty P at the running offset
-        for q in range(nb):
-            if not ident[lvl, q] and rank[lvl, q] == 0:
-                later = P_off[lvl, q + 1:][P_off[lvl, q + 1:] >= 0]
-                P_off[lvl, q] = later[0] if later.size else p_total
-        J_prev = J_cur
-        st = dict(level=lvl, seconds=round(time.time() - t0, 3),
-                  rank_min=int(rank[lvl].min()), rank_max=int(rank[lvl].max()),
-                  rank_mean=float(rank[lvl].mean()), ident=int(ident[lvl].sum()))
-        stats.append(st)
-        if log:
-            log(st)
+                    dev_tasks.append((q, r0, M, cols))
+            sizes = [M * cols.size for _, _, M, cols in dev_tasks]
+            for s0, s1 in _chunks(sizes, budget_el):
+                part = dev_tasks[s0:s1]
+                lay = run.form([t[1] for t in part], [t[2] for t in part], [t[3] for t in part])
+                rk, piv, p_off, p_d = run.column_ids_device(lay, tol)
+                for b, (q, _, _, cols) in enumerate(part):
+                    k, Kb, c0 = int(rk[b]), cols.size, int(lay["col_off"][b])
+                    rank[lvl, q] = k
+                    if k == Kb:
+                        ident[lvl, q] = 1
+                        J_cur[q] = cols
+                    else:
+                        J_cur[q] = cols[piv[c0:c0 + k]]
+                        if k > 0:
+                            P_off[lvl, q] = p_total + p_off[b]
+                if p_d is not None:
+                    ev = torch.cuda.Event()
+                    ev.record(torch.cuda.current_stream(device))
+                    futs.append(copier.submit(_download, len(copies), p_d, ev))
+                    copies.append((p_total, len(copies)))
+                    p_total += p_d.numel()
+            # blocks that keep no column have an empty P at the running offset
+            for q in range(nb):
+                if not ident[lvl, q] and rank[lvl, q] == 0:
+                    later = P_off[lvl, q + 1:][P_off[lvl, q + 1:] >= 0]
+                    P_off[lvl, q] = later[0] if later.size else p_total
+            J_prev = J_cur
+            st = dict(level=lvl, seconds=round(time.time() - t0, 3),
+                      rank_min=int(rank[lvl].min()), rank_max=int(rank[lvl].max()),
+                      rank_mean=float(rank[lvl].mean()), ident=int(ident[lvl].sum()))
+            stats.append(st)
+            if log:
+                log(st)
+    except BaseException:
+        copier.shutdown(wait=True)   # no download is left running behind the error
+        raise
     t0 = time.time()
     copier.shutdown(wait=True)
     for f in futs:
