@@ -262,16 +262,23 @@ __global__ __launch_bounds__(kPanelThreads) void hqr_panel_kernel(Meta md, int p
   }
 }
 
-__global__ __launch_bounds__(kTrailThreads) void hqr_trail_kernel(Meta md, int p0, double *__restrict__ a,
+// Workgroup g runs on XCD g % 8: the groups of one block are numbered so that
+// they all land on XCD b % 8, where they share the panel's reflectors in L2.
+__global__ __launch_bounds__(kTrailThreads) void hqr_trail_kernel(Meta md, int count, int ngroups, int p0,
+                                                                  double *__restrict__ a,
                                                                   const double *__restrict__ tbuf) {
   constexpr int NW = kTrailThreads / 64;
   __shared__ double T[kPanel][kPanel];
-  const int b = blockIdx.x;
+  const int64_t g = blockIdx.x;
+  const int64_t sg = g >> 3;
+  const int b = (int)((sg / ngroups) * 8 + (g & 7));
+  const int gy = (int)(sg % ngroups);
+  if (b >= count) return;
   const int64_t M = md.rows[b];
   const int K = (int)(md.col_off[b + 1] - md.col_off[b]);
   if (!reduce_first(M, K) || p0 >= K) return;
   // a panel with columns to its right is a full one: kPanel reflectors
-  const int first = p0 + kPanel + blockIdx.y * kTrailCols;
+  const int first = p0 + kPanel + gy * kTrailCols;
   if (first >= K) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double *tb = tbuf + (int64_t)b * kPanel * kPanel;
@@ -739,8 +746,11 @@ extern "C" bfmht_status bfmht_column_id(int32_t count, const int64_t *rows, cons
       hipLaunchKernelGGL(hqr_panel_kernel, dim3((unsigned)count), dim3(kPanelThreads), 0, s, md, p0, a, tq);
       const int64_t ntrail = kred - p0 - kPanel;
       if (ntrail > 0) {
-        const dim3 grid((unsigned)count, (unsigned)((ntrail + kTrailCols - 1) / kTrailCols));
-        hipLaunchKernelGGL(hqr_trail_kernel, grid, dim3(kTrailThreads), 0, s, md, p0, a, (const double *)tq);
+        const int ngroups = (int)((ntrail + kTrailCols - 1) / kTrailCols);
+        const int64_t nwg = ((int64_t)(count + 7) / 8) * 8 * ngroups;   // whole rounds of 8 blocks
+        if (nwg >= (int64_t(1) << 31)) return bfmht::set_error(BFMHT_EINVAL, std::string(who) + ": too many blocks");
+        hipLaunchKernelGGL(hqr_trail_kernel, dim3((unsigned)nwg), dim3(kTrailThreads), 0, s, md, (int)count, ngroups,
+                           p0, a, (const double *)tq);
       }
       e0 = hipGetLastError();
     }
