@@ -44,18 +44,22 @@ def host_memory():
 
 def _counter_record(workload):
     """The committed rocprofv3 counter summary of a workload
-    (profiles/hbm_traffic_<workload>.json), or None when it is missing or the
-    kernels have changed since its counters were taken."""
+    (profiles/hbm_traffic_<workload>.json), or None when it is missing or any
+    source it lists (the kernels and the host code that lays out their work)
+    has changed since its counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.json" % workload)
     try:
         with open(path) as f:
             d = json.load(f)
-        with open(os.path.join(ROOT, "paper_2605_21828_amd", "csrc", "kernels.hip"), "rb") as f:
-            cur = hashlib.sha1(f.read()).hexdigest()
+        src = d.get("sources_sha1") or {}
+        for rel, sha in src.items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest() != sha:
+                    return None
     except (OSError, ValueError):
         return None
-    return d if d.get("kernels_hip_sha1") == cur else None
+    return d if src else None
 
 
 def measured_traffic(workload, part="fwd", per="launch"):
@@ -121,11 +125,22 @@ def folded_levels(fs):
     return k
 
 
-def level_bytes(fs, b, s_x):
+def level_bytes(fs, b, s_x, merged=False):
     """Implementation bytes of one forward apply: every level vector it writes
-    (sum of the ranks of a level, b columns; folded levels have none) written
+    (sum of the ranks of a level, b columns; folded levels have none, and a plan
+    that merges the leaf bases into the last level does not form y_L) written
     once and read once."""
-    return 2.0 * float(np.asarray(fs["rank"], dtype=np.int64)[folded_levels(fs):].sum()) * b * s_x
+    rank = np.asarray(fs["rank"], dtype=np.int64)
+    last = int(fs["L"]) if merged else int(fs["L"]) + 1
+    return 2.0 * float(rank[folded_levels(fs):last].sum()) * b * s_x
+
+
+def stage_launches(plan, fs):
+    """Stage launches of one apply in either direction: the plan's stages (L + 2,
+    or L + 1 with merged leaf blocks) less the folded identity levels (the
+    transposed apply sums their copies in one gather-sum launch instead)."""
+    from paper_2605_21828_amd import bfmht as B
+    return B.bfmht_plan_num_stages(plan.handle) - folded_levels(fs)
 
 
 def _blas_threads():
@@ -386,7 +401,8 @@ def bench_sphere(args):
         t_b = event_time(lambda: p.apply_t(ft, out=g), reps, torch)
         outs[prec] = (y.double().cpu().numpy(), g.double().cpu().numpy())
         rec[prec] = {"ms_per_step": ms, "apply_ms": t_f, "apply_transpose_ms": t_b, "tile_shapes": shapes,
-                     "forward_factor_entries": p.stored_fwd}
+                     "forward_factor_entries": p.stored_fwd, "stage_launches": stage_launches(p, fs),
+                     "leaf_merged": p.leaf_merged}
         log("%s step %.3f ms" % (prec, ms))
         del p, ct, ft, y, g
         torch.cuda.empty_cache()
@@ -411,12 +427,13 @@ def bench_sphere(args):
     else:
         base = None
     t_main = rec[main]["apply_ms"]
-    roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=int(fs["L"]) + 2 - folded_levels(fs))
+    launches = rec[main]["stage_launches"]
+    roof = roofline_for(main, rec[main]["forward_factor_entries"], n, m, b, t_main, launches=launches)
     part = "fwd" if main == "bf16x3" else main + "_fwd"   # the counter record's headline part is BF16X3
     roof["traffic"] = measured_traffic("sphere40962", part)
     roof["traffic_unit"] = "bytes per launch"
     roof["mfma_busy_pct_counter"] = measured_mfma_busy("sphere40962", part)
-    roof["level_vector_bytes_per_launch"] = level_bytes(fs, b, 4) / (int(fs["L"]) + 2 - folded_levels(fs))
+    roof["level_vector_bytes_per_launch"] = level_bytes(fs, b, 4, rec[main]["leaf_merged"]) / launches
     res = {
         "metric": "butterfly apply RHS*points/s (%s synthesis + analysis)" % main,
         "value": 2.0 * n * b / (rec[main]["ms_per_step"] * 1e-3), "unit": "RHS*points/s",
@@ -538,7 +555,7 @@ def bench_lsq(args):
     reps = 5
     ms_fwd = event_time(lambda: plan.apply(c), reps, torch)
     ms_bwd = event_time(lambda: plan.apply_t(ft), reps, torch)
-    roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=int(fs["L"]) + 2 - folded_levels(fs))
+    roof = roofline_for("f32", plan.stored_fwd, n, m, 1, ms_fwd, launches=stage_launches(plan, fs))
     roof["traffic"] = measured_traffic(w_key := "iid" + args.workload[len("lsq"):], "fwd")
     roof["traffic_unit"] = "bytes per launch"
     roof["traffic_transposed"] = measured_traffic(w_key, "bwd")
@@ -611,7 +628,7 @@ def bench_inverse(args):
     # algorithmic bytes of one step: both applies' factor bytes (the forward one
     # reads the compact ID blocks) plus their inputs and outputs
     # stage launches of both applies, the input gather and copy sum, and the six vector kernels
-    launches = 2 * (int(fs["L"]) + 2 - folded_levels(fs)) + 2 + 6
+    launches = 2 * stage_launches(p, fs) + 2 + 6
     step_bytes = (FACTOR_BYTES[prec] * (p.stored_fwd + p.stored_t)
                   + 2 * (8 if prec == "f64" else 4) * (n + m) * b)
     achieved = step_bytes / (per_iter * 1e-3) / 1e9
@@ -714,7 +731,7 @@ def bench_latency(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "grid64", "n": n, "m": m, "nrhs": b, "leaf": w["leaf"], "tol": w["tol"],
                    "L": int(fs["L"]), "step": "one apply"},
-        "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=int(fs["L"]) + 2 - folded_levels(fs)),
+        "roofline": dict(roofline_for("f64", plan_f.stored_fwd, n, m, b, t * 1e-3, launches=stage_launches(plan_f, fs)),
                          traffic=measured_traffic("grid64", "f64_fwd"), traffic_unit="bytes per launch",
                          note="latency-bound: the factors are L2/MALL-resident; reported, not a target"),
         "cpu_baseline": base,
@@ -1027,7 +1044,7 @@ def counter_run(args):
         x = torch.randn(((p.m if fwd else p.n), b), dtype=dt, device=dev)
         y = torch.empty(((p.n if fwd else p.m), b), dtype=dt, device=dev)
         run = (lambda: p.apply(x, out=y)) if fwd else (lambda: p.apply_t(x, out=y))
-        launches = int(fs["L"]) + 2 - (folded_levels(fs) if fwd else 0)
+        launches = stage_launches(p, fs)
     run()
     torch.cuda.synchronize()
     for _ in range(count):
@@ -1134,7 +1151,7 @@ def main():
     reps = max(args.steps, 5)
     ms_fwd = event_time(lambda: p32.apply(c32, out=y32), reps, torch)
     ms_bwd = event_time(lambda: p32.apply_t(f32, out=g32), reps, torch)
-    launches = int(fs["L"]) + 2 - folded_levels(fs)   # stage-0, L transfer levels, final stage, less the folded ones
+    launches = stage_launches(p32, fs)   # stage launches of one forward apply
     # the forward apply reads the compact ID blocks (T only): its algorithmic
     # factor entries are the forward pool's, not the full factor count F
     F_fwd = p32.stored_fwd
@@ -1148,7 +1165,20 @@ def main():
         "forward_factor_entries": F_fwd,
         "stage_launches_per_apply": launches,
         "tile_shapes": tuned,
+        "leaf_merged": p32.leaf_merged,
     }
+    if p32.leaf_merged:
+        # the same factors with the leaf bases as a stage of their own (comparison)
+        log("uploading FP32 plan with a separate leaf stage")
+        ps = Plan(fs, "f32", max_nrhs=b, device=dev, leaf_stage=True)
+        if not args.no_tune:
+            tune_plan(ps, fs, b, use_cache=args.cache, log=log)
+        ys, gs = torch.empty_like(y32), torch.empty_like(g32)
+        result_extra["separate_leaf_stage"] = {
+            "apply_ms": event_time(lambda: ps.apply(c32, out=ys), reps, torch),
+            "apply_transpose_ms": event_time(lambda: ps.apply_t(f32, out=gs), reps, torch),
+            "stage_launches_per_apply": stage_launches(ps, fs), "forward_factor_entries": ps.stored_fwd}
+        del ps, ys, gs
     variants_out = {}
 
     # Precision variants on the same inputs: the plain FP64 apply (speedup
@@ -1223,7 +1253,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes32 / launches,
                      # level vectors written by one stage and read by the next: not
                      # algorithmic (intermediate), reported beside it
-                     "impl_bytes_per_launch": level_bytes(fs, b, 4) / launches,
+                     "impl_bytes_per_launch": level_bytes(fs, b, 4, p32.leaf_merged) / launches,
                      "kernel": "stage_kernel<P_F32, forward> (all stage launches of one FP32 apply)",
                      "per_launch_alg_flops": flops / launches,
                      "avg_launch_ms": ms_fwd / launches},

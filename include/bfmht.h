@@ -120,7 +120,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precisio
                                int32_t max_nrhs, bfmht_plan **plan);
 
 /* Plan flags of bfmht_plan_create_ex. */
-#define BFMHT_PLAN_FULL_BLOCKS 1 /* store every ID block as the full P (no compact form) */
+#define BFMHT_PLAN_FULL_BLOCKS 1 /* store every ID block as the full P (no compact form, no merged leaf blocks) */
+#define BFMHT_PLAN_LEAF_STAGE 2  /* keep the leaf bases as a stage of their own (no merged leaf blocks) */
 
 /* bfmht_plan_create with flags (0 = the default of bfmht_plan_create).  By
  * default a transfer or level-0 block whose P has the column-ID structure
@@ -128,15 +129,23 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precisio
  * decomposition, each exactly a unit vector) is applied in compact form in the
  * forward direction: only T is stored and the skeleton rows are added, which
  * saves the identity part's bytes and flops; results agree with the full form
- * up to rounding.  BFMHT_PLAN_FULL_BLOCKS keeps the full P.  EINVAL on unknown
- * flags; otherwise as bfmht_plan_create. */
+ * up to rounding.  BFMHT_PLAN_FULL_BLOCKS keeps the full P.
+ * By default the leaf bases are also merged into the last transfer level
+ * (Sec. 2: f_i = U_i y_{L,i} with y_{L,i} = P_{L,i} x, so the two products are
+ * one with the block U_i P_{L,i}, formed once in FP64 on the host here) when
+ * L >= 1, the last level is not all identities, and the merged blocks hold at
+ * most 1/32 more entries than U_i and the stored P_{L,i} together (the case
+ * when the last level's ranks equal the leaf sizes).  A merged plan has one
+ * stage fewer per direction; its results agree with the separate stages up to
+ * rounding.  BFMHT_PLAN_LEAF_STAGE keeps the separate leaf stage.  EINVAL on
+ * unknown flags; otherwise as bfmht_plan_create. */
 bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *factors, bfmht_precision prec, int32_t max_nrhs,
                                   int32_t flags, bfmht_plan **plan);
 
 /* Factor entries one apply reads (storage and apply cost coincide: every
- * stored block is applied once per vector, Sec. 6.2): transpose = 0 for the forward direction
- * (compact blocks count T only), 1 for the transposed direction (every block
- * in full); -1 if plan is NULL. */
+ * stored block is applied once per vector, Sec. 6.2): transpose = 0 for the
+ * forward direction, 1 for the transposed direction.  Compact blocks count T
+ * only, merged leaf blocks n_i K_i; -1 if plan is NULL. */
 int64_t bfmht_plan_stored_entries(const bfmht_plan *plan, int32_t transpose);
 
 /* Bytes of device memory the plan needs for its factors (the Sec. 2 factor
@@ -210,7 +219,8 @@ bfmht_status bfmht_lsqr(const bfmht_plan *plan, const void *f, int64_t ldf, void
 int64_t bfmht_lsqr_workspace_bytes(const bfmht_plan *plan, int32_t nrhs);
 
 /* Number of stages of one apply (the levels of the Sec. 2 recursion): L + 2 (level 0, the L transfer levels, the
- * leaf stage), numbered in forward order; -1 for NULL.  Leading levels whose
+ * leaf stage), or L + 1 when the leaf bases are merged into the last transfer
+ * level (see bfmht_plan_create_ex), numbered in forward order; -1 for NULL.  Leading levels whose
  * blocks are all identities are folded into the next stage by single applies
  * (their tile shapes then have no effect). */
 int32_t bfmht_plan_num_stages(const bfmht_plan *plan);

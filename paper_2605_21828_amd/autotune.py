@@ -25,14 +25,15 @@ SHAPES = [(r, c) for r in HEIGHTS for c in WIDTHS]
 CACHE = os.environ.get("BFMHT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "bfmht", "tune.json"))
 
 
-def signature(fs, precision, nrhs, stored_fwd=0):
-    """Cache key: the tree shape, the precision, the RHS count and the forward
-    pool size (compact and full-block plans of one factor set tune apart)."""
+def signature(fs, precision, nrhs, stored_fwd=0, stages=0):
+    """Cache key: the tree shape, the precision, the RHS count, the forward
+    pool size and the stage count (compact, full-block and merged-leaf plans of
+    one factor set tune apart)."""
     h = hashlib.sha1()
     for k in ("rank", "ident", "xoff", "koff"):
         h.update(np.ascontiguousarray(fs[k]).tobytes())
-    return "%s|%d|%d|%d|%s|%d|F%d" % (precision, int(fs["n"]), int(fs["m"]), int(fs["L"]), h.hexdigest()[:16], nrhs,
-                                      int(stored_fwd))
+    return "%s|%d|%d|%d|%s|%d|F%d|S%d" % (precision, int(fs["n"]), int(fs["m"]), int(fs["L"]), h.hexdigest()[:16],
+                                          nrhs, int(stored_fwd), int(stages))
 
 
 def _load_cache(path):
@@ -74,7 +75,7 @@ def apply_config(plan, config):
 def tune_plan(plan, fs, nrhs, reps=10, cache_path=CACHE, use_cache=True, log=None):
     """Choose per-stage tile widths for `plan` at this RHS count; returns the config dict."""
     torch = plan.torch
-    key = signature(fs, plan.precision, nrhs, getattr(plan, "stored_fwd", 0))
+    key = signature(fs, plan.precision, nrhs, getattr(plan, "stored_fwd", 0), B.bfmht_plan_num_stages(plan.handle))
     cache = _load_cache(cache_path) if use_cache else {}
     if key in cache:
         apply_config(plan, cache[key])

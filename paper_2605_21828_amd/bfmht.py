@@ -50,7 +50,8 @@ EXPORTED = [
 
 NOALLOC_WORKSPACE_BYTES = 256 << 20  # BFMHT_NOALLOC_WORKSPACE_BYTES
 
-PLAN_FULL_BLOCKS = 1  # plan flag: keep every ID block as the full P (no compact forward form)
+PLAN_FULL_BLOCKS = 1  # plan flag: keep every ID block as the full P (no compact form, no merged leaf blocks)
+PLAN_LEAF_STAGE = 2   # plan flag: keep the leaf bases as a stage of their own
 # mode bits of bfmht_apply_batched
 BATCH_TRANSPOSE, BATCH_PERSISTENT = 1, 2
 
@@ -181,7 +182,7 @@ def bfmht_plan_create(fs, precision, max_nrhs=1):
 
 
 def bfmht_plan_create_ex(fs, precision, max_nrhs=1, flags=0):
-    """bfmht_plan_create with plan flags (PLAN_FULL_BLOCKS); returns the handle."""
+    """bfmht_plan_create with plan flags (PLAN_FULL_BLOCKS, PLAN_LEAF_STAGE); returns the handle."""
     st, keep = factors_struct(fs)
     h = ctypes.c_void_p()
     _check(lib.bfmht_plan_create_ex(ctypes.byref(st), int(precision), int(max_nrhs), int(flags), ctypes.byref(h)),
@@ -329,13 +330,16 @@ class Plan:
 
     apply(c)   -> f = Phi~ c      c: (m,) or (m, b) tensor on the plan's device
     apply_t(f) -> g = Phi~^T f    f: (n,) or (n, b)
-    full_blocks: store every ID block as the full P also for the forward apply
-    (by default blocks with the column-ID structure keep only T there).
+    full_blocks: store every ID block as the full P (by default blocks with the
+    column-ID structure keep only T, and the leaf bases are merged into the last
+    transfer level when that stores about as many entries).
+    leaf_stage: keep the leaf bases as a stage of their own (no merged blocks).
+    leaf_merged (attribute): whether the plan merged them.
     Element type: float64 for precision "f64", float32 otherwise.
     Calls run on the current torch stream of the plan's device.
     """
 
-    def __init__(self, fs, precision="f32", max_nrhs=64, device="cuda", full_blocks=False):
+    def __init__(self, fs, precision="f32", max_nrhs=64, device="cuda", full_blocks=False, leaf_stage=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("bfmht.Plan needs a HIP device; there is no CPU path")
@@ -348,7 +352,9 @@ class Plan:
         self.precision = precision
         self.dtype = torch.float64 if self.prec == F64 else torch.float32
         self.n, self.m, self.L = int(fs["n"]), int(fs["m"]), int(fs["L"])
-        self.handle = bfmht_plan_create_ex(fs, self.prec, max_nrhs, PLAN_FULL_BLOCKS if full_blocks else 0)
+        flags = (PLAN_FULL_BLOCKS if full_blocks else 0) | (PLAN_LEAF_STAGE if leaf_stage else 0)
+        self.handle = bfmht_plan_create_ex(fs, self.prec, max_nrhs, flags)
+        self.leaf_merged = bfmht_plan_num_stages(self.handle) == self.L + 1
         self.stored_fwd = bfmht_plan_stored_entries(self.handle, False)
         self.stored_t = bfmht_plan_stored_entries(self.handle, True)
         nbytes = bfmht_plan_device_bytes(self.handle)

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bfmht.h"
@@ -72,6 +73,7 @@ struct bfmht_plan {
   int64_t stored_fwd = 0;          // factor entries of the forward pool (compact blocks store T only)
   std::vector<int32_t> maps;       // forward jobs' row-index table
   int64_t off_maps = 0;
+  bool leaf_merged = false;        // leaf bases merged into the last transfer level (stages 0..L)
   int nfold = 0;                   // transposed direction: folded all-identity levels (0: every stage runs)
   int fwd_edge = 0;                // forward direction: the first stage that runs (leading all-identity levels skipped)
   int64_t fold_copies = 0;         // copies of each row of c at level nfold-1
@@ -189,10 +191,45 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *f, bfmht_precision prec
 
 namespace {
 
+// M = U P for one leaf: U (n x r) the leaf basis, P (r x k) its block of the
+// last transfer level (NULL: the identity, k = r); all row-major, M n x k.  A P
+// with the column-ID structure [I T] Pi^T takes U itself in its skeleton
+// columns and U T in the others.
+void leaf_product(const double *U, int64_t n, int64_t r, const double *P, int64_t k, double *M) {
+  if (n == 0 || k == 0) return;
+  if (!P) {
+    std::memcpy(M, U, (size_t)(n * k) * sizeof(double));
+    return;
+  }
+  std::vector<int32_t> jc, jsk;
+  const bool cmp = split_id(P, r, k, jc, jsk);
+  if (!cmp) {   // general P: every column by the product
+    jc.resize(k);
+    for (int64_t c = 0; c < k; ++c) jc[c] = (int32_t)c;
+    jsk.clear();
+  }
+  const int64_t kt = (int64_t)jc.size();
+  std::vector<double> T((size_t)(r * kt)), row((size_t)kt);
+  for (int64_t b = 0; b < r; ++b)
+    for (int64_t c = 0; c < kt; ++c) T[b * kt + c] = P[b * k + jc[c]];
+  for (int64_t a = 0; a < n; ++a) {
+    std::fill(row.begin(), row.end(), 0.0);
+    for (int64_t b = 0; b < r; ++b) {
+      const double u = U[a * r + b];
+      const double *t = T.data() + b * kt;
+      for (int64_t c = 0; c < kt; ++c) row[c] += u * t[c];
+    }
+    for (int64_t c = 0; c < kt; ++c) M[a * k + jc[c]] = row[c];
+    for (size_t b = 0; b < jsk.size(); ++b) M[a * k + jsk[b]] = U[a * r + (int64_t)b];
+  }
+}
+
 // Body of bfmht_plan_create_ex after argument checks; may throw std::bad_alloc
 // (the caller turns that into a status).  *out is set only on success.
+// merge_leaf: apply each leaf basis and its last transfer block as one block
+// when that stores about as many entries (see below).
 bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32_t max_nrhs, bool compact_ids,
-                        bfmht_plan **out) {
+                        bool merge_leaf, bfmht_plan **out) {
   std::unique_ptr<bfmht_plan> owner(new bfmht_plan());
   bfmht_plan *p = owner.get();
   p->prec = prec;
@@ -246,8 +283,40 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
     for (int t = 0; t < A; ++t) r += f->rank[(lvl - 1) * nb + q1 + t];
     return r;
   };
+  // Leading levels whose blocks are all identities (folded, see below).
+  int nfold = 0;
+  while (nfold <= L) {
+    bool all = true;
+    for (int64_t q = 0; q < nb && all; ++q) all = f->ident[nfold * nb + q] != 0;
+    if (!all) break;
+    ++nfold;
+  }
+  // Leaf bases merged into the last transfer level.  f_i = U_i y_{L,i} and
+  // y_{L,i} = P_{L,i} x, so the two products are one with the block U_i P_{L,i}
+  // (n_i x K_i, K_i the block's input rows).  When the last level's ranks equal
+  // the leaf sizes (full-rank leaf blocks, the usual case) that block has as
+  // many entries as U_i and the compact P_{L,i} together, and applying it saves
+  // a stage per direction and the write and read of y_L.  Merged when the
+  // merged blocks hold at most 1/32 more entries than the separate ones, the
+  // last level runs (it is not folded away) and L >= 1; the transposed
+  // direction then reads the gathered f rows of each leaf as its consumer rows.
+  bool merge = false;
+  if (merge_leaf && L >= 1 && nfold <= L) {
+    int64_t sep = 0, mrg = 0;
+    std::vector<int32_t> jc, jsk;
+    for (int64_t i = 0; i < nb; ++i) {
+      const int64_t n_i = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i], k = rin_of(L, i);
+      int64_t pe = 0;
+      if (!f->ident[L * nb + i] && r * k > 0)
+        pe = split_id(f->P + f->P_off[L * nb + i], r, k, jc, jsk) ? r * (int64_t)jc.size() : r * k;
+      sep += n_i * r + pe;
+      mrg += n_i * k;
+    }
+    merge = 32 * mrg <= 33 * sep;
+  }
+  p->leaf_merged = merge;
   std::vector<int64_t> bidx_P((size_t)(L + 1) * nb, -1);
-  for (int lvl = 0; lvl <= L; ++lvl)
+  for (int lvl = 0; lvl <= (merge ? L - 1 : L); ++lvl)
     for (int64_t q = 0; q < nb; ++q) {
       if (f->ident[lvl * nb + q]) continue;
       const int64_t r = f->rank[lvl * nb + q], k = rin_of(lvl, q);
@@ -261,11 +330,40 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       blocks.push_back(std::move(b));
     }
   std::vector<int64_t> bidx_U(nb, -1);
+  std::vector<std::vector<double>> merged;   // U_i P_{L,i} per leaf (merged plans)
+  if (merge) {
+    merged.resize(nb);
+    for (int64_t i = 0; i < nb; ++i) merged[i].assign((size_t)((f->xoff[i + 1] - f->xoff[i]) * rin_of(L, i)), 0.0);
+    // leaves in parallel (each worker takes every nth leaf); a failed worker
+    // reports through `bad` and the plan fails as out of memory
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, nb, (int64_t)std::thread::hardware_concurrency()}));
+    std::vector<char> bad(nt, 0);
+    auto work = [&](int t) {
+      try {
+        for (int64_t i = t; i < nb; i += nt) {
+          const int64_t n_i = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i], k = rin_of(L, i);
+          if (r == 0) continue;   // a rank-0 block: M stays zero
+          const bool id = f->ident[L * nb + i] != 0 || k == 0;
+          leaf_product(n_i * r ? f->U + f->U_off[i] : nullptr, n_i, r, id ? nullptr : f->P + f->P_off[L * nb + i], k,
+                       merged[i].data());
+        }
+      } catch (...) {
+        bad[t] = 1;
+      }
+    };
+    std::vector<std::thread> pool_t;
+    for (int t = 1; t < nt; ++t) pool_t.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool_t) th.join();
+    for (char b : bad)
+      if (b) throw std::bad_alloc();
+  }
   for (int64_t i = 0; i < nb; ++i) {
-    const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = f->rank[L * nb + i];
+    const int64_t rows = f->xoff[i + 1] - f->xoff[i], r = merge ? rin_of(L, i) : f->rank[L * nb + i];
     woff_U[i] = pool;
     bidx_U[i] = (int64_t)blocks.size();
-    blocks.push_back({rows * r ? f->U + f->U_off[i] : nullptr, rows, r, false, {}, {}});
+    const double *src = merge ? merged[i].data() : f->U + f->U_off[i];
+    blocks.push_back({rows * r ? src : nullptr, rows, r, false, {}, {}});
     pool += rows * ldw_of(r);
     p->stored_fwd += rows * r;
   }
@@ -432,9 +530,13 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   auto cons_of = [&](int lvl, int64_t q) -> ConsIn {
     return {bidx_P[lvl * nb + q], f->ident[lvl * nb + q] != 0, f->rank[lvl * nb + q], (int32_t)off[lvl][q]};
   };
-  for (int lvl = 0; lvl <= L + 1; ++lvl) {
+  // Merged plans end with stage L: forward jobs of the leaf stage's form (rows
+  // scattered to the points' order) that read level L-1, transposed jobs of
+  // level L's form whose consumers are the merged leaf blocks.
+  const int last = merge ? L : L + 1;
+  for (int lvl = 0; lvl <= last; ++lvl) {
     StageDesc s{};
-    s.kind = lvl == 0 ? 0 : (lvl <= L ? 1 : 2);
+    s.kind = lvl == 0 ? 0 : (lvl < last ? 1 : 2);
     s.level = lvl;
     s.fjob0 = (int64_t)fj.size();
     s.bjob0[0] = (int64_t)bj.size();
@@ -450,13 +552,17 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       }
     } else if (lvl <= L) {
       const int64_t nf = ipow(A, L - lvl);
+      const bool ml = merge && lvl == L;   // merged last level (nf = 1, block q is leaf q)
       for (int64_t i = 0; i < ipow(A, lvl); ++i)
         for (int64_t j = 0; j < nf; ++j) {
           const int64_t q = i * nf + j, q1 = child0(lvl, q);
           const bool id = f->ident[lvl * nb + q] != 0;
           const int64_t k = rin_of(lvl, q);
-          fj.push_back(fjob(id ? -1 : woff_P[lvl * nb + q], bidx_P[lvl * nb + q], f->rank[lvl * nb + q], k,
-                            off[lvl - 1][q1], off[lvl][q]));
+          if (ml)
+            fj.push_back(fjob(woff_U[q], bidx_U[q], f->xoff[q + 1] - f->xoff[q], k, off[lvl - 1][q1], f->xoff[q]));
+          else
+            fj.push_back(fjob(id ? -1 : woff_P[lvl * nb + q], bidx_P[lvl * nb + q], f->rank[lvl * nb + q], k,
+                              off[lvl - 1][q1], off[lvl][q]));
         }
       // a transposed job owns the A consecutive input blocks of one parent pp
       // and frequency node j, and sums the products of their A consumers (the
@@ -468,8 +574,13 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
             const int64_t q1 = pp * A * nf + A * j;
             int64_t K = 0;
             for (int t = 0; t < A; ++t) K += f->rank[(lvl - 1) * nb + q1 + t];
-            const ConsIn cs[2] = {cons_of(lvl, (A * pp + 2 * part) * nf + j),
-                                  cons_of(lvl, (A * pp + 2 * part + 1) * nf + j)};
+            ConsIn cs[2] = {cons_of(lvl, (A * pp + 2 * part) * nf + j),
+                            cons_of(lvl, (A * pp + 2 * part + 1) * nf + j)};
+            if (ml)   // consumers are merged leaf blocks: their rows are leaf rows of the gathered f
+              for (int c = 0; c < 2; ++c) {
+                const int64_t qc = A * pp + 2 * part + c;
+                cs[c] = {bidx_U[qc], false, (int32_t)(f->xoff[qc + 1] - f->xoff[qc]), (int32_t)f->xoff[qc]};
+              }
             BwdJob J = bjob((int32_t)K, (int32_t)off[lvl - 1][q1], 2, cs);
             J.accum = part;
             bj.push_back(J);
@@ -485,7 +596,7 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
       }
     }
     s.nfjob = (int64_t)fj.size() - s.fjob0;
-    if (s.kind != 1) s.nbjob[0] = (int64_t)bj.size() - s.bjob0[0];
+    if (lvl == 0 || lvl > L) s.nbjob[0] = (int64_t)bj.size() - s.bjob0[0];
     p->stages.push_back(s);
   }
   p->tpool_elems = tpool;
@@ -498,13 +609,6 @@ bfmht_status plan_build(const bfmht_factors_host *f, bfmht_precision prec, int32
   // Identity jobs of stage e become row-gather jobs (a compact job with nothing
   // to reduce and every row a skeleton row).  The transposed direction keeps its
   // stages: there the copies of one row of c are summed.
-  int nfold = 0;
-  while (nfold <= L) {
-    bool all = true;
-    for (int64_t q = 0; q < nb && all; ++q) all = f->ident[nfold * nb + q] != 0;
-    if (!all) break;
-    ++nfold;
-  }
   if (nfold > 0) {
     // pi over the rows of level nfold-1
     std::vector<int64_t> pi((size_t)off[0][nb]);
@@ -636,13 +740,14 @@ bfmht_status bfmht_plan_create_ex(const bfmht_factors_host *f, bfmht_precision p
                                   bfmht_plan **out) {
   if (!out) return fail(BFMHT_EINVAL, "plan output pointer is NULL");
   *out = nullptr;
-  if (flags & ~BFMHT_PLAN_FULL_BLOCKS) return fail(BFMHT_EINVAL, "unknown plan flags");
+  if (flags & ~(BFMHT_PLAN_FULL_BLOCKS | BFMHT_PLAN_LEAF_STAGE)) return fail(BFMHT_EINVAL, "unknown plan flags");
   if (prec < BFMHT_F64 || prec > BFMHT_BF16X3) return fail(BFMHT_EINVAL, "unknown precision");
   if (max_nrhs < 1) return fail(BFMHT_EINVAL, "max_nrhs must be >= 1");
   bfmht_status st = validate(f);
   if (st != BFMHT_OK) return st;
   try {
-    return plan_build(f, prec, max_nrhs, (flags & BFMHT_PLAN_FULL_BLOCKS) == 0, out);
+    const bool full = (flags & BFMHT_PLAN_FULL_BLOCKS) != 0;
+    return plan_build(f, prec, max_nrhs, !full, !full && (flags & BFMHT_PLAN_LEAF_STAGE) == 0, out);
   } catch (const std::bad_alloc &) {
     return fail(BFMHT_ENOSPACE, "host memory exhausted while building the plan");
   } catch (...) {
@@ -757,10 +862,11 @@ int64_t level_buffer_bytes(const bfmht_plan *p, int32_t nrhs) {
 }
 
 // The transposed apply first gathers f's rows into tree order, into the level
-// buffer its leaf stage reads (the one level L+1 maps to).
+// buffer its last stage reads (the leaf stage, level L+1, or the merged last
+// level L).
 int gather_input(const bfmht_plan *p, const void *in, int64_t ldin, int32_t nrhs, char *const buf[2], void *stream) {
   return launch_gather_rows((int)p->esz, in, ldin, reinterpret_cast<const int32_t *>(p->dev + p->off_perm), p->n,
-                            buf[(p->L + 1) & 1], nrhs, nrhs, stream);
+                            buf[p->stages.back().level & 1], nrhs, nrhs, stream);
 }
 
 bfmht_status run_apply(const bfmht_plan *p, bool fwd, const void *in, int64_t ldin, void *out, int64_t ldout,

@@ -19,14 +19,17 @@ def _partition(rng, total, parts, allow_empty=True):
 
 
 def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=True, identity_values=False,
-                      p_id_form=0.0, ident_levels=0, arity=2):
+                      p_id_form=0.0, ident_levels=0, arity=2, full_rank_leaves=False):
     """Random factor set.  identity_values=True makes every P the identity and
     every U_i a 0/1 selection so that the apply is an exact permutation.
     p_id_form: probability that a non-identity block with 0 < rank < inputs has
     the column-ID form P = [I T] Pi^T (r random columns hold e_1 .. e_r).
     ident_levels: levels 0 .. ident_levels-1 hold identity blocks only.
     arity: children per tree node (k-ary trees); a block's inputs are the k
-    children of its frequency node under the parent of its space node."""
+    children of its frequency node under the parent of its space node.
+    full_rank_leaves: a non-identity block of the last level takes rank
+    min(inputs, leaf rows), as in factorizations whose leaves are smaller than
+    their blocks' numerical rank (max_rank does not apply there)."""
     rng = np.random.default_rng(seed)
     nb = arity ** L
     perm = rng.permutation(n).astype(np.int32)
@@ -51,6 +54,8 @@ def random_factor_set(seed, n, m, L, max_rank=None, p_ident=0.25, allow_empty=Tr
                 continue
             hi = rin if max_rank is None else min(rin, max_rank)
             r = int(rng.integers(0, hi + 1))
+            if full_rank_leaves and lvl == L:
+                r = min(rin, int(xoff[q + 1] - xoff[q]))
             rank[lvl, q] = r
             P_off[lvl, q] = off
             blk = rng.standard_normal((r, rin)) / np.sqrt(max(rin, 1))

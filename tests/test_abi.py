@@ -187,11 +187,56 @@ def _id_saving(fs):
     return save
 
 
+def _leaf_merge(fs):
+    """(whether a default plan merges the leaf bases into the last level, the
+    entries U_i and the stored P_{L,i} take apart, the entries of the merged
+    blocks U_i P_{L,i}), counted from the factor set (binary trees)."""
+    L, nb = int(fs["L"]), 1 << int(fs["L"])
+    if L < 1 or all(fs["ident"][: L + 1].reshape(-1)):
+        return False, 0, 0
+    sep = mrg = 0
+    for q in range(nb):
+        r, n_i = int(fs["rank"][L, q]), int(fs["xoff"][q + 1] - fs["xoff"][q])
+        q1 = (q >> 1) * 2
+        k = int(fs["rank"][L - 1, q1] + fs["rank"][L - 1, q1 + 1])
+        pe = 0
+        if not fs["ident"][L, q] and r * k > 0:
+            P = fs["P"][fs["P_off"][L, q]:fs["P_off"][L, q] + r * k].reshape(r, k)
+            unit = [np.flatnonzero((P[:, j] == 1.0) & (np.count_nonzero(P[:, j]) == 1)) for j in range(k)]
+            idform = 0 < r < k and len({int(u[0]) for u in unit if u.size}) == r
+            pe = r * (k - r) if idform else r * k
+        sep += n_i * r + pe
+        mrg += n_i * k
+    return 32 * mrg <= 33 * sep, sep, mrg
+
+
 @pytest.mark.parametrize("p_id_form", [0.0, 0.5, 1.0])
-def test_stored_entries_compact_and_full(p_id_form):
-    fs = random_factor_set(7, 400, 300, 4, max_rank=40, p_id_form=p_id_form)
+@pytest.mark.parametrize("full_rank_leaves", [False, True])
+def test_stored_entries_compact_and_full(p_id_form, full_rank_leaves):
+    """Compact blocks drop their identity part in both directions; a default
+    plan merges the leaf bases into the last level exactly when the merged
+    blocks are at most 1/32 larger, and then stores n_i K_i for each leaf
+    instead of U_i and P_{L,i}."""
+    fs = random_factor_set(7, 400, 300, 4, max_rank=40, p_id_form=p_id_form, full_rank_leaves=full_rank_leaves)
     full = int(fs["P"].size + fs["U"].size)
-    h = B.bfmht_plan_create_ex(fs, B.F32, 4, 0)
+    merge, sep, mrg = _leaf_merge(fs)
+    assert merge or not full_rank_leaves   # full-rank leaf blocks always pay for the merge
+    hs = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_LEAF_STAGE)
+    try:
+        assert B.bfmht_plan_num_stages(hs) == int(fs["L"]) + 2
+        assert B.bfmht_plan_stored_entries(hs, False) == full - _id_saving(fs)
+        assert B.bfmht_plan_stored_entries(hs, True) == full - _id_saving(fs)
+    finally:
+        B.bfmht_plan_destroy(hs)
+    hm = B.bfmht_plan_create_ex(fs, B.F32, 4, 0)
+    try:
+        assert B.bfmht_plan_num_stages(hm) == int(fs["L"]) + (1 if merge else 2)
+        expect = full - _id_saving(fs) - (sep - mrg if merge else 0)
+        assert B.bfmht_plan_stored_entries(hm, False) == expect
+        assert B.bfmht_plan_stored_entries(hm, True) == expect
+    finally:
+        B.bfmht_plan_destroy(hm)
+    h = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_LEAF_STAGE)
     hf = B.bfmht_plan_create_ex(fs, B.F32, 4, B.PLAN_FULL_BLOCKS)
     try:
         assert B.bfmht_plan_stored_entries(hf, True) == full
@@ -213,7 +258,7 @@ def test_id_block_with_a_perturbed_skeleton_stays_full():
     P = fs["P"].copy()
     P[np.flatnonzero(P == 1.0)[0]] = 1.0 + 2.0 ** -40   # one skeleton entry no longer exactly 1
     bad = dict(fs, P=P)
-    h = B.bfmht_plan_create_ex(bad, B.F64, 1, 0)
+    h = B.bfmht_plan_create_ex(bad, B.F64, 1, B.PLAN_LEAF_STAGE)
     try:
         assert B.bfmht_plan_stored_entries(h, False) == int(P.size + fs["U"].size) - _id_saving(bad)
         assert B.bfmht_plan_stored_entries(h, True) == int(P.size + fs["U"].size) - _id_saving(bad)
@@ -224,7 +269,7 @@ def test_id_block_with_a_perturbed_skeleton_stays_full():
 
 def test_plan_create_ex_rejects_unknown_flags(good):
     with pytest.raises(B.BfmhtError) as e:
-        B.bfmht_plan_create_ex(good, B.F32, 1, 2)
+        B.bfmht_plan_create_ex(good, B.F32, 1, 4)
     assert e.value.status == B.EINVAL
     assert B.bfmht_plan_stored_entries(None, 0) == -1
 
@@ -238,10 +283,20 @@ def test_fourier_factor_set_is_applied_in_compact_form():
     fs, _ = fio.fourier_factors(wl.points_for(w), w["m"], w["leaf"], w["tol"], workers=1, cache=False)
     full = int(fs["P"].size + fs["U"].size)
     save = _id_saving(fs)
-    h = B.bfmht_plan_create_ex(fs, B.F64, 1, 0)
+    h = B.bfmht_plan_create_ex(fs, B.F64, 1, B.PLAN_LEAF_STAGE)
     try:
         assert save > 0
         assert B.bfmht_plan_stored_entries(h, False) == B.bfmht_plan_stored_entries(h, True) == full - save
+    finally:
+        B.bfmht_plan_destroy(h)
+    # its last level has full-rank leaf blocks, so a default plan merges the
+    # leaf bases into it, at no more entries than the blocks apart
+    merge, sep, mrg = _leaf_merge(fs)
+    assert merge and mrg <= sep
+    h = B.bfmht_plan_create_ex(fs, B.F64, 1, 0)
+    try:
+        assert B.bfmht_plan_num_stages(h) == int(fs["L"]) + 1
+        assert B.bfmht_plan_stored_entries(h, False) == full - save - sep + mrg
     finally:
         B.bfmht_plan_destroy(h)
     # every stored transfer/level-0 block with 0 < rank < inputs has the ID form:
@@ -266,9 +321,10 @@ def test_fourier_factor_set_is_applied_in_compact_form():
 
 
 def test_tile_shapes_are_host_state(good):
-    # stage count L + 2, default 64 x 0 (smallest width covering nrhs), the six
-    # legal shapes accepted per direction and stage, anything else rejected
-    h = B.bfmht_plan_create(good, B.F32, 4)
+    # stage count L + 2 (separate leaf stage), default 64 x 0 (smallest width
+    # covering nrhs), the six legal shapes accepted per direction and stage,
+    # anything else rejected
+    h = B.bfmht_plan_create_ex(good, B.F32, 4, B.PLAN_LEAF_STAGE)
     try:
         S = B.bfmht_plan_num_stages(h)
         assert S == int(good["L"]) + 2
