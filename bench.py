@@ -1068,6 +1068,8 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cache", action="store_true", help="reuse a factor file cached under $BFMHT_CACHE")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile widths")
+    ap.add_argument("--no-leaf-compare", action="store_true",
+                    help="skip the comparison plan with a separate leaf stage (kernel traces of the headline apply)")
     ap.add_argument("--precision", default=None, help="headline precision of the sphere workload")
     ap.add_argument("--arity", type=int, default=2, choices=(2, 4),
                     help="tree arity of the nonuniform-square workloads (4: quadtree and 4-ary mode tree)")
@@ -1167,7 +1169,7 @@ def main():
         "tile_shapes": tuned,
         "leaf_merged": p32.leaf_merged,
     }
-    if p32.leaf_merged:
+    if p32.leaf_merged and not args.no_leaf_compare:
         # the same factors with the leaf bases as a stage of their own (comparison)
         log("uploading FP32 plan with a separate leaf stage")
         ps = Plan(fs, "f32", max_nrhs=b, device=dev, leaf_stage=True)
