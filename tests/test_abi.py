@@ -160,29 +160,39 @@ def test_destroy_null_is_noop():
     assert B.lib.bfmht_version().startswith(b"bfmht")
 
 
+def _inputs(fs, lvl, q):
+    """Input rows of block (lvl, q): its frequency leaf's modes at level 0, else the
+    ranks of its arity consecutive input blocks of level lvl-1."""
+    a = int(fs.get("arity", 2)) or 2
+    L = int(fs["L"])
+    if lvl == 0:
+        return int(fs["koff"][q + 1] - fs["koff"][q])
+    nf = a ** (L - lvl)
+    i, j = divmod(q, nf)
+    q1 = (i // a) * a * nf + a * j
+    return int(fs["rank"][lvl - 1, q1:q1 + a].sum())
+
+
+def _is_id_form(P, r, k):
+    unit = [np.flatnonzero((P[:, j] == 1.0) & (np.count_nonzero(P[:, j]) == 1)) for j in range(k)]
+    return 0 < r < k and len({int(u[0]) for u in unit if u.size}) == r
+
+
 def _id_saving(fs):
     """Entries the compact form drops: r^2 per ID-form block (read from the
     blocks directly)."""
-    L, nb = int(fs["L"]), 1 << int(fs["L"])
+    L = int(fs["L"])
+    nb = (int(fs.get("arity", 2)) or 2) ** L
     save = 0
     for lvl in range(L + 1):
-        nf = 1 << (L - lvl)
         for q in range(nb):
             if fs["ident"][lvl, q] or fs["P_off"][lvl, q] < 0:
                 continue
-            r = int(fs["rank"][lvl, q])
-            if lvl == 0:
-                k = int(fs["koff"][q + 1] - fs["koff"][q])
-            else:
-                i, j = divmod(q, nf)
-                q1 = (i >> 1) * 2 * nf + 2 * j
-                k = int(fs["rank"][lvl - 1, q1] + fs["rank"][lvl - 1, q1 + 1])
+            r, k = int(fs["rank"][lvl, q]), _inputs(fs, lvl, q)
             if not 0 < r < k:
                 continue
             P = fs["P"][fs["P_off"][lvl, q]:fs["P_off"][lvl, q] + r * k].reshape(r, k)
-            unit = [np.flatnonzero((P[:, j] == 1.0) & (np.count_nonzero(P[:, j]) == 1)) for j in range(k)]
-            rows = {int(u[0]) for u in unit if u.size}
-            if len(rows) == r:
+            if _is_id_form(P, r, k):
                 save += r * r
     return save
 
@@ -190,21 +200,18 @@ def _id_saving(fs):
 def _leaf_merge(fs):
     """(whether a default plan merges the leaf bases into the last level, the
     entries U_i and the stored P_{L,i} take apart, the entries of the merged
-    blocks U_i P_{L,i}), counted from the factor set (binary trees)."""
-    L, nb = int(fs["L"]), 1 << int(fs["L"])
+    blocks U_i P_{L,i}), counted from the factor set."""
+    L = int(fs["L"])
+    nb = (int(fs.get("arity", 2)) or 2) ** L
     if L < 1 or all(fs["ident"][: L + 1].reshape(-1)):
         return False, 0, 0
     sep = mrg = 0
     for q in range(nb):
-        r, n_i = int(fs["rank"][L, q]), int(fs["xoff"][q + 1] - fs["xoff"][q])
-        q1 = (q >> 1) * 2
-        k = int(fs["rank"][L - 1, q1] + fs["rank"][L - 1, q1 + 1])
+        r, n_i, k = int(fs["rank"][L, q]), int(fs["xoff"][q + 1] - fs["xoff"][q]), _inputs(fs, L, q)
         pe = 0
         if not fs["ident"][L, q] and r * k > 0:
             P = fs["P"][fs["P_off"][L, q]:fs["P_off"][L, q] + r * k].reshape(r, k)
-            unit = [np.flatnonzero((P[:, j] == 1.0) & (np.count_nonzero(P[:, j]) == 1)) for j in range(k)]
-            idform = 0 < r < k and len({int(u[0]) for u in unit if u.size}) == r
-            pe = r * (k - r) if idform else r * k
+            pe = r * (k - r) if _is_id_form(P, r, k) else r * k
         sep += n_i * r + pe
         mrg += n_i * k
     return 32 * mrg <= 33 * sep, sep, mrg
@@ -212,12 +219,14 @@ def _leaf_merge(fs):
 
 @pytest.mark.parametrize("p_id_form", [0.0, 0.5, 1.0])
 @pytest.mark.parametrize("full_rank_leaves", [False, True])
-def test_stored_entries_compact_and_full(p_id_form, full_rank_leaves):
+@pytest.mark.parametrize("arity", [2, 4])
+def test_stored_entries_compact_and_full(p_id_form, full_rank_leaves, arity):
     """Compact blocks drop their identity part in both directions; a default
     plan merges the leaf bases into the last level exactly when the merged
     blocks are at most 1/32 larger, and then stores n_i K_i for each leaf
     instead of U_i and P_{L,i}."""
-    fs = random_factor_set(7, 400, 300, 4, max_rank=40, p_id_form=p_id_form, full_rank_leaves=full_rank_leaves)
+    fs = random_factor_set(7, 400, 300, 4 if arity == 2 else 2, max_rank=40, p_id_form=p_id_form,
+                           full_rank_leaves=full_rank_leaves, arity=arity)
     full = int(fs["P"].size + fs["U"].size)
     merge, sep, mrg = _leaf_merge(fs)
     assert merge or not full_rank_leaves   # full-rank leaf blocks always pay for the merge

@@ -41,3 +41,31 @@ def test_level_bytes_counts_every_level_vector_twice():
     fs["ident"][0] = 1
     assert bench.folded_levels(fs) == 1
     assert bench.level_bytes(fs, 8, 4) == 2.0 * 7 * 8 * 4
+
+
+def test_merged_plans_form_no_last_level_vector():
+    # with the leaf bases merged into the last level, y_L is never written
+    fs = {"L": 1, "rank": np.array([[1, 2], [3, 4]], dtype=np.int32), "ident": np.zeros((2, 2), np.uint8)}
+    assert bench.level_bytes(fs, 8, 4, merged=True) == 2.0 * 3 * 8 * 4
+
+
+def test_counter_records_follow_their_sources(tmp_path, monkeypatch):
+    """A counter record counts only while every source it lists has the hash it
+    was taken with; a record that lists no sources never counts."""
+    import hashlib
+    import json
+    src = tmp_path / "src" / "k.hip"
+    src.parent.mkdir()
+    src.write_text("kernel v1\n")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"sources_sha1": {"src/k.hip": hashlib.sha1(b"kernel v1\n").hexdigest()},
+           "fwd": {"hbm_bytes_per_launch": 5.0, "hbm_bytes_per_apply": 35.0}, "fwd_mfma": {"mfma_busy_pct": 40.0}}
+    (prof / "hbm_traffic_w.json").write_text(json.dumps(rec))
+    (prof / "hbm_traffic_old.json").write_text(json.dumps({"kernels_hip_sha1": "x", "fwd": rec["fwd"]}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("w") == 5.0 and bench.measured_traffic("w", per="apply") == 35.0
+    assert bench.measured_mfma_busy("w") == 40.0
+    assert bench.measured_traffic("old") is None and bench.measured_traffic("missing") is None
+    src.write_text("kernel v2\n")
+    assert bench.measured_traffic("w") is None and bench.measured_mfma_busy("w") is None
