@@ -104,3 +104,25 @@ def test_quadtree_is_a_partition_into_quadrants():
     assert sorted(p3.tolist()) == list(range(1000)) and x3[-1] == 1000 and len(x3) == 65
     # 4-ary frequency leaves are the binary index tree's leaves at twice the depth
     assert np.array_equal(frequency_tree(1000, 3, 4), frequency_tree(1000, 6))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_device_build_chunks_cover_the_level_within_the_budget(seed):
+    """The device build processes a level's blocks in chunks: consecutive ranges
+    that cover every block once, in order, each within the memory budget unless
+    it is a single block larger than the budget, and each as long as the budget
+    allows (the next block would not fit)."""
+    from paper_2605_21828_amd.factor.device_build import _chunks
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.integers(0, 100, size=int(rng.integers(0, 40)))]
+    if seed == 5 and sizes:
+        sizes[len(sizes) // 2] = 1000   # one block above the budget
+    budget = 250
+    ch = _chunks(sizes, budget)
+    assert [i for a, b in ch for i in range(a, b)] == list(range(len(sizes)))
+    for a, b in ch:
+        assert b > a
+        total = sum(sizes[a:b])
+        assert total <= budget or b - a == 1
+        if b < len(sizes):
+            assert total + sizes[b] > budget
