@@ -132,7 +132,8 @@ bfmht_status bfmht_plan_create(const bfmht_factors_host *factors, bfmht_precisio
  * up to rounding.  BFMHT_PLAN_FULL_BLOCKS keeps the full P.
  * By default the leaf bases are also merged into the last transfer level
  * (Sec. 2: f_i = U_i y_{L,i} with y_{L,i} = P_{L,i} x, so the two products are
- * one with the block U_i P_{L,i}, formed once in FP64 on the host here) when
+ * one with the block U_i P_{L,i}, formed once in FP64 on the host here, by up
+ * to 16 threads that the call starts and joins) when
  * L >= 1, the last level is not all identities, and the merged blocks hold at
  * most 1/32 more entries than U_i and the stored P_{L,i} together (the case
  * when the last level's ranks equal the leaf sizes).  A merged plan has one
