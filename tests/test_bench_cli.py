@@ -69,3 +69,20 @@ def test_counter_records_follow_their_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("old") is None and bench.measured_traffic("missing") is None
     src.write_text("kernel v2\n")
     assert bench.measured_traffic("w") is None and bench.measured_mfma_busy("w") is None
+
+
+def test_stage_launches_follow_the_plan():
+    """Launches per apply come from the plan: L + 1 stages with merged leaf
+    blocks, L + 2 with the separate leaf stage, less the folded levels."""
+    from types import SimpleNamespace
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from factor_gen import random_factor_set
+    from paper_2605_21828_amd import bfmht as B
+    fs = random_factor_set(31, 600, 256, 4, max_rank=40, ident_levels=1, p_id_form=0.5, full_rank_leaves=True)
+    assert bench.folded_levels(fs) == 1
+    for flags, stages in ((0, 5), (B.PLAN_LEAF_STAGE, 6)):
+        h = B.bfmht_plan_create_ex(fs, B.F32, 4, flags)
+        try:
+            assert bench.stage_launches(SimpleNamespace(handle=h), fs) == stages - 1
+        finally:
+            B.bfmht_plan_destroy(h)
